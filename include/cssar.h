@@ -1,0 +1,149 @@
+/*
+ * cssar.h -- C ABI of the MI355X (gfx950) library for fast compressed-sensing
+ * SAR imaging with an approximated observation operator.
+ *
+ * Method (Fang, Xu, Zhang, Hong, Wu, "Fast Compressed Sensing SAR Imaging
+ * based on Approximated Observation"):
+ *   - M is a matched-filter focusing chain (Section III.B, eq. (focus)); here
+ *     the chirp-scaling algorithm named in Section III.D.1:
+ *         M(Y) = F_eta^-1 [ Phi3 o F_tau^-1 [ Phi2 o F_tau [ Phi1 o F_eta Y ] ] ]
+ *   - G = M^-1 is the approximated observation (Section III.B), obtained by
+ *     inverting every step (Section III.C rules i) and ii)):
+ *         G(X) = F_eta^-1 [ Phi1* o F_tau^-1 [ Phi2* o F_tau [ Phi3* o F_eta X ] ] ]
+ *     With unitary DFTs and unimodular phases, G^H = M exactly (Theorem 1).
+ *   - The solver is the iterative thresholding algorithm eq. (th2d) /
+ *     Algorithm 1 with X^(0) = 0, step mu = 1 and complex soft threshold
+ *     eq. (L12) at lambda.
+ *   Phase screens (turns = radians / 2 pi), with D(f) = sqrt(1 - (c f/(2 fc v))^2),
+ *   Km(f) = Kr / (1 - Kr c r_ref f^2 / (2 v^2 fc^3 D^3)) (Km = Kr if src = 0),
+ *   tau_j = 2 r_ref / c + (j - N_r/2) / fs, R0_j = c tau_j / 2:
+ *     Phi1 = exp(i pi Km (1/D - 1) (tau_j - 2 r_ref / (c D))^2)
+ *     Phi2 = exp(i pi D / Km f_tau^2) exp(i 4 pi r_ref f_tau (1/D - 1) / c)
+ *     Phi3 = exp(i 4 pi fc R0_j D / c) exp(-i 4 pi Km / c^2 (1 - D) (R0_j - r_ref)^2 / D^2)
+ *   with f_eta = prf nu(k)/N_a, f_tau = fs nu(l)/N_r, nu the signed (fftfreq
+ *   order) frequency index.
+ *
+ * Data layout: a scene or raw-data array is N_a x N_r complex64 (interleaved
+ * float re, im; torch.complex64), row-major, row = one range line (azimuth
+ * index i), column = one azimuth line (range index j).  All array pointers
+ * are DEVICE pointers on the current HIP device unless stated otherwise.
+ * Supported lengths: N in {64, 128, ..., 8192} and {768, 1536, 3072} for
+ * both N_a and N_r.
+ *
+ * Ownership: the caller owns every array (inputs, outputs, workspace).  The
+ * operator owns only its O(N_a + N_r) coefficient and twiddle tables and a
+ * small status block, released by cssar_destroy_operator.  Inputs are never
+ * written.  Outputs must not alias inputs or the workspace unless stated.
+ *
+ * Errors: every call returns CSSAR_OK (0) or a negative code; arguments are
+ * validated on the host before any HIP call.  Kernels are enqueued
+ * asynchronously on the given stream (a hipStream_t, passed as void*; NULL =
+ * the null stream).  Errors found on the device (a non-finite residual norm)
+ * are reported by cssar_sync_status.  cssar_last_error returns a thread-local
+ * message for the last non-zero status.  Calls sharing one operator must not
+ * run concurrently on different streams (they share its status block).
+ */
+#ifndef CSSAR_H
+#define CSSAR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CSSAR_OK = 0,
+  CSSAR_EINVAL = -1,       /* null pointer, non-positive size or parameter, lambda < 0 */
+  CSSAR_EUNSUPPORTED = -2, /* a length outside the supported set, f_dc != 0 */
+  CSSAR_EHIP = -3,         /* HIP runtime error (message in cssar_last_error) */
+  CSSAR_ENONFINITE = -4,   /* NaN or Inf met in a residual norm */
+  CSSAR_ENOMEM = -5        /* device allocation of the operator tables failed */
+};
+
+/* Radar parameters, SI units, double precision (stripmap model, Section
+ * II.A; Table 2 lists the same fields). */
+typedef struct cssar_params {
+  double fc;    /* carrier frequency f0 [Hz] */
+  double Kr;    /* range chirp rate [Hz/s] (bandwidth / pulse duration) */
+  double Tp;    /* pulse duration [s] (not used by G or M) */
+  double fs;    /* range sampling rate [Hz] */
+  double prf;   /* pulse repetition frequency [Hz] */
+  double v;     /* effective radar velocity [m/s] */
+  double r_ref; /* reference (scene-centre) slant range [m], at column N_r/2 */
+  double ba;    /* processed Doppler bandwidth [Hz] (not used by G or M) */
+  double f_dc;  /* Doppler centroid [Hz]; must be 0 */
+  int src;      /* 1: secondary range compression in Km; 0: Km = Kr */
+} cssar_params;
+
+typedef struct cssar_op cssar_op;
+
+/* Build an operator for an n_az x n_rg grid: FP64 per-Doppler-bin and
+ * per-range-column coefficient vectors, FP32 twiddle tables, kernel plan.
+ * Host call; allocates the operator's small device tables on the current
+ * device.  *out is set only on success. */
+int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** out);
+
+/* Release an operator and its tables (NULL is accepted). */
+int cssar_destroy_operator(cssar_op* op);
+
+/* Workspace bytes the caller must provide:
+ *   mode 0: cssar_apply_G / cssar_apply_GH   (0 bytes: outputs double as scratch)
+ *   mode 1: cssar_ita_solve                  (one N_a x N_r complex64 array)
+ * Returns 0 for a NULL operator or an unknown mode. */
+size_t cssar_workspace_size(const cssar_op* op, int mode);
+
+/* y_out = G x (approximated observation, Section III.B).  x and y_out are
+ * N_a x N_r complex64; ws may be NULL.  y_out must not alias x. */
+int cssar_apply_G(cssar_op* op, const void* x, void* y_out, void* ws, void* stream);
+
+/* x_out = G^H y = M y (focusing chain, Theorem 1).  Same layout rules. */
+int cssar_apply_GH(cssar_op* op, const void* y, void* x_out, void* ws, void* stream);
+
+/* Pack a row-major N_a x N_r byte mask (nonzero = sampled) into the bit
+ * layout the solver reads: bit (i*N_r + j) of the 32-bit word array, LSB
+ * first.  mask_bits must hold ceil(N_a*N_r/32) words. */
+int cssar_pack_mask(const cssar_op* op, const void* mask_bytes, void* mask_bits, void* stream);
+
+/* Iterative thresholding, eq. (th2d) / Algorithm 1:
+ *   X^(0) = 0;  for t < iters:  R = m o (y - G X^(t));  X^(t+1) = S_lambda(X^(t) + M R)
+ * y: N_a x N_r complex64 raw data (entries outside the mask are ignored);
+ * mask_bits: packed mask (cssar_pack_mask); lambda >= 0; iters >= 1;
+ * x_out: N_a x N_r complex64 result X^(iters);
+ * resid_hist: NULL or a device array of iters floats receiving ||R^(t)||^2;
+ * ws: cssar_workspace_size(op, 1) bytes.  x_out must not alias y or ws. */
+int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda,
+                    int iters, void* x_out, float* resid_hist, void* ws, void* stream);
+
+/* Synchronise the stream and report a deferred device-side error of this
+ * operator (CSSAR_ENONFINITE if a residual norm was NaN/Inf), clearing it. */
+int cssar_sync_status(cssar_op* op, void* stream);
+
+/* Thread-local message for the last non-zero status returned on this thread. */
+const char* cssar_last_error(void);
+
+/* Per-launch timing, for measurement only.  While enabled, every pass kernel
+ * an operator enqueues is bracketed by two HIP events on its stream.
+ * cssar_profile_read waits for those events, returns the summed elapsed
+ * milliseconds and launch counts per pass kind, and forgets them.  Kinds:
+ * 0 row pass with Phi2 (inside M), 1 row pass with Phi2* (inside G),
+ * 2 column forward transform + Phi1, 3 column forward + Phi3*, 4 column
+ * Phi1* + inverse, 5 column Phi3 + inverse, 6 column update/threshold pass,
+ * 7 column residual pass. */
+#define CSSAR_PROFILE_KINDS 8
+int cssar_profile_enable(cssar_op* op, int on);
+int cssar_profile_read(cssar_op* op, double* ms_sum, long* counts);
+
+/* Whether a length is supported (1) or not (0). */
+int cssar_supported_length(int n);
+
+/* Kernel plan of a length, for inspection: elements per thread, number of
+ * radix passes and the radices (radices must hold 8 ints).  Returns 0 or
+ * CSSAR_EUNSUPPORTED. */
+int cssar_plan_info(int n, int* elems_per_thread, int* n_passes, int* radices);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSSAR_H */

@@ -1,0 +1,500 @@
+// C ABI of the library: operator construction (FP64 coefficient vectors,
+// twiddle tables, launch plan), operator application G / G^H and the
+// iterative thresholding solver.  See include/cssar.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cssar.h"
+#include "cssar_kernels.hpp"
+#include "cssar_table.hpp"
+
+using namespace cssar;
+
+namespace {
+
+constexpr double kC = 299792458.0;
+constexpr int kMaxPartials = 8192;
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(CSSAR_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),       \
+                  __FILE__, __LINE__);                                              \
+  } while (0)
+
+const KernelTable* table_for(int n) {
+  switch (n) {
+#define CSSAR_CASE(NN) \
+  case NN:             \
+    return kernel_table_##NN();
+    CSSAR_FOR_EACH_LENGTH(CSSAR_CASE)
+#undef CSSAR_CASE
+    default:
+      return nullptr;
+  }
+}
+
+int signed_bin(int k, int n) { return k < (n + 1) / 2 ? k : k - n; }
+
+}  // namespace
+
+struct cssar_op {
+  int na = 0, nr = 0;
+  cssar_params p{};
+  int device = 0;
+  int cus = 0;
+  const KernelTable* ka = nullptr;  // azimuth length N_a (column passes)
+  const KernelTable* kr = nullptr;  // range length N_r (row passes)
+  double2* rowc1 = nullptr;         // per Doppler bin: Phi1 (a1, d1)
+  double2* rowc2 = nullptr;         //                  Phi2 (a2, b2)
+  double2* rowc3 = nullptr;         //                  Phi3 (D, b3)
+  double2* colc = nullptr;          // per range column: (P_j, dtau_j)
+  float2* tw_a = nullptr;           // w_{N_a}^k
+  float2* tw_r = nullptr;           // w_{N_r}^k
+  float* partials = nullptr;        // per-block partial sums
+  unsigned* counter = nullptr;      // [0] last-block counter, [1] status bits
+  int grid_row = 0;
+  int grid_col[CK_COUNT] = {};
+  // optional per-launch HIP event timing (cssar_profile_enable)
+  bool profiling = false;
+  struct Rec {
+    int kind;
+    hipEvent_t start, stop;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+// FP64 coefficient vectors of the three phase screens (turns = radians/2pi).
+//   D(f) = sqrt(1 - (lambda f / (2 v))^2), D_ref = 1 (zero Doppler centroid)
+//   Km(f) = Kr / (1 - Kr c r_ref f^2 / (2 v^2 fc^3 D^3))   (Km = Kr if !src)
+//   Phi1 = a1 (dtau - d1)^2, a1 = Km (1/D - 1) / 2, d1 = 2 r_ref (1/D - 1) / c
+//   Phi2 = (a2 nu + b2) nu,  a2 = D / (2 Km) (fs/N_r)^2, b2 = 2 r_ref (1/D - 1) / c (fs/N_r)
+//   Phi3 = D P_j + b3 dtau^2, b3 = -Km (1 - D) / (2 D^2), P_j = fc tau_j
+void build_coefficients(const cssar_params& p, int na, int nr, std::vector<double2>& r1,
+                        std::vector<double2>& r2, std::vector<double2>& r3,
+                        std::vector<double2>& cc) {
+  const double lam = kC / p.fc;
+  const double df = p.fs / nr;
+  r1.resize(na);
+  r2.resize(na);
+  r3.resize(na);
+  for (int k = 0; k < na; ++k) {
+    const double f = p.prf * signed_bin(k, na) / na;
+    const double u = lam * f / (2.0 * p.v);
+    const double D = std::sqrt(1.0 - u * u);
+    double Km = p.Kr;
+    if (p.src) Km = p.Kr / (1.0 - p.Kr * kC * p.r_ref * f * f / (2.0 * p.v * p.v * p.fc * p.fc * p.fc * D * D * D));
+    const double invD1 = 1.0 / D - 1.0;
+    r1[k] = make_double2(0.5 * Km * invD1, 2.0 * p.r_ref * invD1 / kC);
+    r2[k] = make_double2(0.5 * D / Km * df * df, 2.0 * p.r_ref * invD1 / kC * df);
+    r3[k] = make_double2(D, -0.5 * Km * (1.0 - D) / (D * D));
+  }
+  cc.resize(nr);
+  for (int j = 0; j < nr; ++j) {
+    const double dtau = (j - nr / 2) / p.fs;
+    const double tau = 2.0 * p.r_ref / kC + dtau;
+    cc[j] = make_double2(p.fc * tau, dtau);
+  }
+}
+
+void build_twiddles(int n, std::vector<float2>& t) {
+  t.resize(n);
+  for (int k = 0; k < n; ++k) {
+    // exp(-2 pi i k / n), evaluated in FP64 and rounded to FP32
+    const double a = 2.0 * M_PI * (double)k / (double)n;
+    t[k] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
+  }
+}
+
+int check_params(const cssar_params* p) {
+  if (!p) return fail(CSSAR_EINVAL, "params is NULL");
+  const double vals[] = {p->fc, p->Kr, p->fs, p->prf, p->v, p->r_ref};
+  const char* names[] = {"fc", "Kr", "fs", "prf", "v", "r_ref"};
+  for (int i = 0; i < 6; ++i)
+    if (!(vals[i] > 0.0) || !std::isfinite(vals[i]))
+      return fail(CSSAR_EINVAL, "parameter %s must be positive and finite", names[i]);
+  if (p->f_dc != 0.0) return fail(CSSAR_EUNSUPPORTED, "non-zero Doppler centroid is not supported");
+  // every Doppler bin must stay below the migration singularity
+  const double umax = (kC / p->fc) * (p->prf / 2.0) / (2.0 * p->v);
+  if (!(umax < 1.0)) return fail(CSSAR_EINVAL, "PRF too high for the velocity and wavelength");
+  return CSSAR_OK;
+}
+
+int check_op(const cssar_op* op) {
+  if (!op) return fail(CSSAR_EINVAL, "operator is NULL");
+  return CSSAR_OK;
+}
+
+int occupancy(const void* fn, int block) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, 0) != hipSuccess || n < 1) n = 1;
+  return n;
+}
+
+int grid_for(int work, int cus, int per_cu) {
+  int g = std::min(work, cus * per_cu);
+  if (g >= 16) g -= g % 8;  // lets the kernels renumber blocks per XCD
+  return std::max(g, 1);
+}
+
+ColArgs col_args(const cssar_op* op) {
+  ColArgs a{};
+  a.colc = op->colc;
+  a.tw = op->tw_a;
+  a.na = op->na;
+  a.nr = op->nr;
+  a.scale = 1.0f / (float)op->na;
+  a.mu = 1.0f;
+  a.partials = op->partials;
+  a.counter = op->counter;
+  a.status = op->counter + 1;
+  return a;
+}
+
+RowArgs row_args(const cssar_op* op, const void* in, void* out, int conj) {
+  RowArgs a{};
+  a.in = (const float2*)in;
+  a.out = (float2*)out;
+  a.rowc2 = op->rowc2;
+  a.tw = op->tw_r;
+  a.na = op->na;
+  a.conj = conj;
+  a.scale = 1.0f / (float)op->nr;
+  return a;
+}
+
+hipEvent_t take_event(cssar_op* op) {
+  if (!op->pool.empty()) {
+    hipEvent_t e = op->pool.back();
+    op->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Kind ids of cssar_profile_read: 0/1 row pass (Phi2 / Phi2*), 2 + column kernel id.
+template <typename F>
+int timed(cssar_op* op, int kind, hipStream_t s, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (op->profiling) {
+    a = take_event(op);
+    b = take_event(op);
+    if (!a || !b) return fail(CSSAR_EHIP, "hipEventCreate failed");
+    HIP_TRY(hipEventRecord(a, s));
+  }
+  HIP_TRY(launch());
+  if (op->profiling) {
+    HIP_TRY(hipEventRecord(b, s));
+    op->recs.push_back({kind, a, b});
+  }
+  return CSSAR_OK;
+}
+
+int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s) {
+  return timed(op, a.conj ? 1 : 0, s, [&] { return op->kr->row(a, op->grid_row, s); });
+}
+
+int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
+  return timed(op, 2 + which, s, [&] { return op->ka->col[which](a, op->grid_col[which], s); });
+}
+
+}  // namespace
+
+extern "C" {
+
+int cssar_supported_length(int n) { return table_for(n) != nullptr; }
+
+int cssar_plan_info(int n, int* elems_per_thread, int* n_passes, int* radices) {
+  const KernelTable* t = table_for(n);
+  if (!t) return fail(CSSAR_EUNSUPPORTED, "length %d is not supported", n);
+  if (elems_per_thread) *elems_per_thread = t->E;
+  if (n_passes) *n_passes = t->passes;
+  if (radices)
+    for (int i = 0; i < 8; ++i) radices[i] = t->radices[i];
+  return CSSAR_OK;
+}
+
+const char* cssar_last_error(void) { return g_last_error.c_str(); }
+
+int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** out) {
+  if (!out) return fail(CSSAR_EINVAL, "out is NULL");
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (n_az <= 0 || n_rg <= 0) return fail(CSSAR_EINVAL, "grid sizes must be positive");
+  const KernelTable* ka = table_for(n_az);
+  const KernelTable* kr = table_for(n_rg);
+  if (!ka) return fail(CSSAR_EUNSUPPORTED, "azimuth length %d is not supported", n_az);
+  if (!kr) return fail(CSSAR_EUNSUPPORTED, "range length %d is not supported", n_rg);
+  if (n_rg % ka->C != 0 || n_rg % 32 != 0)
+    return fail(CSSAR_EUNSUPPORTED, "range length %d incompatible with the column tile", n_rg);
+
+  std::vector<double2> r1, r2, r3, cc;
+  build_coefficients(*p, n_az, n_rg, r1, r2, r3, cc);
+  for (int k = 0; k < n_az; ++k)
+    if (!std::isfinite(r1[k].x) || !std::isfinite(r2[k].x) || !std::isfinite(r3[k].y))
+      return fail(CSSAR_EINVAL, "parameters give non-finite phase coefficients");
+  std::vector<float2> ta, tr;
+  build_twiddles(n_az, ta);
+  build_twiddles(n_rg, tr);
+
+  cssar_op* op = new cssar_op();
+  op->na = n_az;
+  op->nr = n_rg;
+  op->p = *p;
+  op->ka = ka;
+  op->kr = kr;
+  auto cleanup = [&](int code) {
+    cssar_destroy_operator(op);
+    return code;
+  };
+  if (hipGetDevice(&op->device) != hipSuccess) return cleanup(fail(CSSAR_EHIP, "hipGetDevice failed"));
+  if (hipDeviceGetAttribute(&op->cus, hipDeviceAttributeMultiprocessorCount, op->device) != hipSuccess)
+    return cleanup(fail(CSSAR_EHIP, "cannot query the compute unit count"));
+  const size_t rowb = sizeof(double2) * n_az;
+  void* mem = nullptr;
+  const size_t total = 3 * rowb + sizeof(double2) * n_rg + sizeof(float2) * (n_az + n_rg) +
+                       sizeof(float) * kMaxPartials + 4 * sizeof(unsigned) + 1024;
+  if (hipMalloc(&mem, total) != hipSuccess) return cleanup(fail(CSSAR_ENOMEM, "hipMalloc of %zu bytes failed", total));
+  char* base = (char*)mem;
+  op->rowc1 = (double2*)base;
+  op->rowc2 = (double2*)(base + rowb);
+  op->rowc3 = (double2*)(base + 2 * rowb);
+  op->colc = (double2*)(base + 3 * rowb);
+  op->tw_a = (float2*)((char*)op->colc + sizeof(double2) * n_rg);
+  op->tw_r = op->tw_a + n_az;
+  op->partials = (float*)(op->tw_r + n_rg);
+  op->counter = (unsigned*)(op->partials + kMaxPartials);
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemcpy(op->rowc1, r1.data(), rowb, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(op->rowc2, r2.data(), rowb, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(op->rowc3, r3.data(), rowb, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(op->colc, cc.data(), sizeof(double2) * n_rg, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(op->tw_a, ta.data(), sizeof(float2) * n_az, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(op->tw_r, tr.data(), sizeof(float2) * n_rg, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(op->counter, 0, 4 * sizeof(unsigned));
+  if (e != hipSuccess) return cleanup(fail(CSSAR_EHIP, "uploading operator tables: %s", hipGetErrorString(e)));
+
+  const int row_work = (n_az + kr->LR - 1) / kr->LR;
+  op->grid_row = grid_for(row_work, op->cus, occupancy(kr->row_fn, kr->RT));
+  const int col_work = n_rg / ka->C;
+  for (int w = 0; w < CK_COUNT; ++w) {
+    op->grid_col[w] = grid_for(col_work, op->cus, occupancy(ka->col_fn[w], ka->CT));
+    if (op->grid_col[w] > kMaxPartials) op->grid_col[w] = kMaxPartials;
+  }
+  *out = op;
+  return CSSAR_OK;
+}
+
+int cssar_destroy_operator(cssar_op* op) {
+  if (!op) return CSSAR_OK;
+  for (auto& r : op->recs) {
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  for (auto e : op->pool) (void)hipEventDestroy(e);
+  if (op->rowc1) (void)hipFree(op->rowc1);
+  delete op;
+  return CSSAR_OK;
+}
+
+size_t cssar_workspace_size(const cssar_op* op, int mode) {
+  if (!op) return 0;
+  const size_t n = (size_t)op->na * op->nr * sizeof(float2);
+  switch (mode) {
+    case 0:
+      return 0;
+    case 1:
+      return n;
+    default:
+      return 0;
+  }
+}
+
+int cssar_apply_GH(cssar_op* op, const void* y, void* x_out, void* ws, void* stream) {
+  (void)ws;
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (!y || !x_out) return fail(CSSAR_EINVAL, "NULL array");
+  if (y == x_out) return fail(CSSAR_EINVAL, "output aliases input");
+  hipStream_t s = (hipStream_t)stream;
+  // x = F_eta^-1 [Phi3 o F_tau^-1 [Phi2 o F_tau [Phi1 o F_eta y]]], x_out as scratch
+  ColArgs a = col_args(op);
+  a.in0 = (const float2*)y;
+  a.out = (float2*)x_out;
+  a.rowc = op->rowc1;
+  if ((rc = launch_col(op, CK_FWD1, a, s))) return rc;
+  if ((rc = launch_row(op, row_args(op, x_out, x_out, 0), s))) return rc;
+  a.in0 = (const float2*)x_out;
+  a.rowc = op->rowc3;
+  return launch_col(op, CK_INV3, a, s);
+}
+
+int cssar_apply_G(cssar_op* op, const void* x, void* y_out, void* ws, void* stream) {
+  (void)ws;
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (!x || !y_out) return fail(CSSAR_EINVAL, "NULL array");
+  if (x == y_out) return fail(CSSAR_EINVAL, "output aliases input");
+  hipStream_t s = (hipStream_t)stream;
+  // y = F_eta^-1 [Phi1* o F_tau^-1 [Phi2* o F_tau [Phi3* o F_eta x]]]
+  ColArgs a = col_args(op);
+  a.in0 = (const float2*)x;
+  a.out = (float2*)y_out;
+  a.rowc = op->rowc3;
+  a.conj = 1;
+  if ((rc = launch_col(op, CK_FWD3, a, s))) return rc;
+  if ((rc = launch_row(op, row_args(op, y_out, y_out, 1), s))) return rc;
+  a.in0 = (const float2*)y_out;
+  a.rowc = op->rowc1;
+  return launch_col(op, CK_INV1, a, s);
+}
+
+int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters,
+                    void* x_out, float* resid_hist, void* ws, void* stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (!y || !mask_bits || !x_out || !ws) return fail(CSSAR_EINVAL, "NULL array");
+  if (iters < 1) return fail(CSSAR_EINVAL, "iters must be >= 1");
+  if (!(lambda >= 0.0f) || !std::isfinite(lambda)) return fail(CSSAR_EINVAL, "lambda must be finite and >= 0");
+  if (x_out == y || x_out == ws || ws == y) return fail(CSSAR_EINVAL, "x_out, y and ws must not alias");
+  hipStream_t s = (hipStream_t)stream;
+  float2* X = (float2*)x_out;  // holds Xt = Phi3* o F_eta X between iterations
+  float2* P = (float2*)ws;     // Wg / R / W, updated in place by each pass
+  ColArgs a = col_args(op);
+  a.y = (const float2*)y;
+  a.mask = (const uint32_t*)mask_bits;
+  a.sigma = lambda * a.mu;
+  for (int t = 0; t < iters; ++t) {
+    const bool last = t == iters - 1;
+    a.hist_out = resid_hist ? resid_hist + t : nullptr;
+    if (t == 0) {
+      // R(0) = m o y (G X(0) = 0): P = Phi1 o F_eta R
+      ColArgs f = a;
+      f.in0 = (const float2*)y;
+      f.out = P;
+      f.rowc = op->rowc1;
+      f.flags = 1;
+      if ((rc = launch_col(op, CK_FWD1, f, s))) return rc;
+    } else {
+      // Wg = F_tau^-1 Phi2* F_tau Xt ; then R = m o (y - G X), P = Phi1 o F_eta R
+      if ((rc = launch_row(op, row_args(op, X, P, 1), s))) return rc;
+      ColArgs r = a;
+      r.in0 = P;
+      r.out = P;
+      r.rowc = op->rowc1;
+      if ((rc = launch_col(op, CK_R, r, s))) return rc;
+    }
+    // W = F_tau^-1 Phi2 F_tau P  (so that F_eta M R = Phi3 o W)
+    if ((rc = launch_row(op, row_args(op, P, P, 0), s))) return rc;
+    ColArgs u = a;
+    u.in0 = X;
+    u.in1 = P;
+    u.out = X;
+    u.rowc = op->rowc3;
+    u.flags = (t == 0 ? 1 : 0) | (last ? 2 : 0);
+    u.hist_out = nullptr;
+    if ((rc = launch_col(op, CK_A, u, s))) return rc;
+  }
+  return CSSAR_OK;
+}
+
+int cssar_profile_enable(cssar_op* op, int on) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  op->profiling = on != 0;
+  return CSSAR_OK;
+}
+
+int cssar_profile_read(cssar_op* op, double* ms_sum, long* counts) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (!ms_sum || !counts) return fail(CSSAR_EINVAL, "NULL output");
+  for (int k = 0; k < CSSAR_PROFILE_KINDS; ++k) {
+    ms_sum[k] = 0.0;
+    counts[k] = 0;
+  }
+  for (auto& r : op->recs) {
+    HIP_TRY(hipEventSynchronize(r.stop));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.start, r.stop));
+    if (r.kind >= 0 && r.kind < CSSAR_PROFILE_KINDS) {
+      ms_sum[r.kind] += ms;
+      counts[r.kind] += 1;
+    }
+    op->pool.push_back(r.start);
+    op->pool.push_back(r.stop);
+  }
+  op->recs.clear();
+  return CSSAR_OK;
+}
+
+int cssar_sync_status(cssar_op* op, void* stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  unsigned st = 0;
+  HIP_TRY(hipMemcpy(&st, op->counter + 1, sizeof st, hipMemcpyDeviceToHost));
+  if (st) {
+    unsigned zero = 0;
+    HIP_TRY(hipMemcpy(op->counter + 1, &zero, sizeof zero, hipMemcpyHostToDevice));
+    if (st & 1u) return fail(CSSAR_ENONFINITE, "non-finite residual norm");
+  }
+  return CSSAR_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ mask packing --
+namespace {
+__global__ void pack_mask_kernel(const unsigned char* __restrict__ m, uint32_t* __restrict__ bits, size_t n) {
+  const size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nw = (n + 31) / 32;
+  if (w >= nw) return;
+  uint32_t word = 0;
+  const size_t base = w * 32;
+  for (int i = 0; i < 32; ++i) {
+    const size_t idx = base + i;
+    if (idx < n && m[idx]) word |= 1u << i;
+  }
+  bits[w] = word;
+}
+}  // namespace
+
+extern "C" int cssar_pack_mask(const cssar_op* op, const void* mask_bytes, void* mask_bits, void* stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (!mask_bytes || !mask_bits) return fail(CSSAR_EINVAL, "NULL array");
+  const size_t n = (size_t)op->na * op->nr;
+  const size_t nw = (n + 31) / 32;
+  const int block = 256;
+  const unsigned grid = (unsigned)((nw + block - 1) / block);
+  hipLaunchKernelGGL(pack_mask_kernel, dim3(grid), dim3(block), 0, (hipStream_t)stream,
+                     (const unsigned char*)mask_bytes, (uint32_t*)mask_bits, n);
+  HIP_TRY(hipGetLastError());
+  return CSSAR_OK;
+}

@@ -1,0 +1,421 @@
+// Device-side building blocks for gfx950 (CDNA4, wave64): complex helpers,
+// register radix kernels, LDS-staged Stockham FFT passes, FP64-argument
+// phase generation and the fused row/column pass kernels of one
+// approximated-observation operator application or ITA iteration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cssar_plan.hpp"
+
+namespace cssar {
+
+// ---------------------------------------------------------------- complex --
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV> __device__ __forceinline__ float2 mul_mi(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// --------------------------------------------------------- radix kernels --
+// In-place DFT of R values held in registers: out[k] = sum_n in[n] w^(n k),
+// w = exp(-2 pi i / R) (forward) or its conjugate (INV).
+template <bool INV> __device__ __forceinline__ void dft2(float2& a0, float2& a1) {
+  float2 t = a0;
+  a0 = cadd(t, a1);
+  a1 = csub(t, a1);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  float2 t2 = cadd(a1, a3), t3 = mul_mi<INV>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(float2& a0, float2& a1, float2& a2) {
+  const float h = 0.86602540378443864676f;  // sqrt(3)/2
+  float2 t = cadd(a1, a2), d = csub(a1, a2);
+  float2 m = make_float2(fmaf(-0.5f, t.x, a0.x), fmaf(-0.5f, t.y, a0.y));
+  // -i h d (forward) / +i h d (inverse)
+  float2 r = mul_mi<INV>(cscale(d, h));
+  a0 = cadd(a0, t);
+  a1 = cadd(m, r);
+  a2 = csub(m, r);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* a) {
+  // even/odd split: E = DFT4(a0,a2,a4,a6), O = DFT4(a1,a3,a5,a7),
+  // X[k] = E[k] + w8^k O[k], X[k+4] = E[k] - w8^k O[k]
+  dft4<INV>(a[0], a[2], a[4], a[6]);
+  dft4<INV>(a[1], a[3], a[5], a[7]);
+  const float r = 0.70710678118654752440f;
+  float2 o1 = a[3], o2 = a[5], o3 = a[7];
+  // w8^1 = (1 - i)/sqrt2 (fwd), (1 + i)/sqrt2 (inv)
+  o1 = INV ? make_float2((o1.x - o1.y) * r, (o1.x + o1.y) * r)
+           : make_float2((o1.x + o1.y) * r, (o1.y - o1.x) * r);
+  o2 = mul_mi<INV>(o2);
+  // w8^3 = (-1 - i)/sqrt2 (fwd), (-1 + i)/sqrt2 (inv)
+  o3 = INV ? make_float2((-o3.x - o3.y) * r, (o3.x - o3.y) * r)
+           : make_float2((o3.y - o3.x) * r, (-o3.x - o3.y) * r);
+  float2 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6], o0 = a[1];
+  a[0] = cadd(e0, o0);
+  a[4] = csub(e0, o0);
+  a[1] = cadd(e1, o1);
+  a[5] = csub(e1, o1);
+  a[2] = cadd(e2, o2);
+  a[6] = csub(e2, o2);
+  a[3] = cadd(e3, o3);
+  a[7] = csub(e3, o3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft16(float2* a) {
+  // 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.
+  // Y_{n2}[k1] = DFT4_{n1}(a[4 n1 + n2]); Z = Y * w16^(n2 k1); X[k1 + 4 k2] = DFT4_{n2}(Z[n2][k1])
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(a[n2], a[4 + n2], a[8 + n2], a[12 + n2]);
+  // now a[4 k1 + n2] holds Y_{n2}[k1]
+  const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
+  const float r = 0.70710678118654752440f;
+  // twiddles w16^(n2 k1) for n2, k1 in 1..3: exponents 1,2,3,2,4,6,3,6,9
+  auto tw = [&](float2 x, int e) -> float2 {
+    // w16^e, e in {1,2,3,4,6,9}; forward w = exp(-2 pi i e / 16)
+    float cr, ci;
+    switch (e) {
+      case 1: cr = c1; ci = -s1; break;
+      case 2: cr = r; ci = -r; break;
+      case 3: cr = s1; ci = -c1; break;
+      case 4: cr = 0.f; ci = -1.f; break;
+      case 6: cr = -r; ci = -r; break;
+      default: cr = -c1; ci = s1; break;  // 9: exp(-2 pi i 9/16) = -c1 + i s1
+    }
+    if (INV) ci = -ci;
+    return make_float2(fmaf(x.x, cr, -x.y * ci), fmaf(x.x, ci, x.y * cr));
+  };
+  a[4 * 1 + 1] = tw(a[4 * 1 + 1], 1);
+  a[4 * 1 + 2] = tw(a[4 * 1 + 2], 2);
+  a[4 * 1 + 3] = tw(a[4 * 1 + 3], 3);
+  a[4 * 2 + 1] = tw(a[4 * 2 + 1], 2);
+  a[4 * 2 + 2] = mul_mi<INV>(a[4 * 2 + 2]);
+  a[4 * 2 + 3] = tw(a[4 * 2 + 3], 6);
+  a[4 * 3 + 1] = tw(a[4 * 3 + 1], 3);
+  a[4 * 3 + 2] = tw(a[4 * 3 + 2], 6);
+  a[4 * 3 + 3] = tw(a[4 * 3 + 3], 9);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<INV>(a[4 * k1 + 0], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3]);
+  // a[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 index
+  float2 t[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) t[i] = a[i];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = t[4 * k1 + k2];
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft_reg(float2* a) {
+  if constexpr (R == 2) {
+    dft2<INV>(a[0], a[1]);
+  } else if constexpr (R == 3) {
+    dft3<INV>(a[0], a[1], a[2]);
+  } else if constexpr (R == 4) {
+    dft4<INV>(a[0], a[1], a[2], a[3]);
+  } else if constexpr (R == 8) {
+    dft8<INV>(a);
+  } else {
+    static_assert(R == 16, "radix");
+    dft16<INV>(a);
+  }
+}
+
+// ------------------------------------------------------- sin/cos in turns --
+// sin and cos of 2 pi r for |r| <= 1/8 by their Taylor series (degree 9 and
+// 10; truncation below 2e-9 at |2 pi r| = pi/4), then a quarter-turn
+// rotation by q.  Coefficients are (2 pi)^k / k! with alternating signs.
+__device__ __forceinline__ float2 cis_quadrant(float r, int q) {
+  const float r2 = r * r;
+  const float S1 = 6.28318530717958647693f, S3 = -41.341702240399760234f,
+              S5 = 81.6052492760750542034f, S7 = -76.7058597530613858416f,
+              S9 = 42.058693944897653145f;
+  const float C2 = -19.7392088021787172377f, C4 = 64.939394022668291491f,
+              C6 = -85.456817206693727736f, C8 = 60.2446413718766603627f,
+              C10 = -26.4262567833743974529f;
+  float s = fmaf(r2, S9, S7);
+  s = fmaf(r2, s, S5);
+  s = fmaf(r2, s, S3);
+  s = fmaf(r2, s, S1);
+  s = s * r;
+  float c = fmaf(r2, C10, C8);
+  c = fmaf(r2, c, C6);
+  c = fmaf(r2, c, C4);
+  c = fmaf(r2, c, C2);
+  c = fmaf(r2, c, 1.0f);
+  // rotate by q quarter turns: (c, s) -> (-s, c) per quarter
+  float cc = (q & 1) ? -s : c;
+  float ss = (q & 1) ? c : s;
+  if (q & 2) {
+    cc = -cc;
+    ss = -ss;
+  }
+  return make_float2(cc, ss);
+}
+
+// Reduced phase: remainder r (|r| <= 1/8 turn, FP32) and quarter-turn count q.
+struct Turns {
+  float r;
+  int q;
+};
+
+// Reduce an FP64 phase in turns modulo 1 and to the nearest quarter turn in
+// FP64; only the remainder is rounded to FP32.
+__device__ __forceinline__ Turns reduce_turns(double t) {
+  double f = t - floor(t);
+  double q = rint(4.0 * f);
+  Turns o;
+  o.r = (float)fma(q, -0.25, f);
+  o.q = (int)q;
+  return o;
+}
+
+// exp(2 pi i t) for an FP64 phase in turns.
+__device__ __forceinline__ float2 cis_turns(double t) {
+  Turns u = reduce_turns(t);
+  return cis_quadrant(u.r, u.q);
+}
+
+// ------------------------------------------------------------ LDS layout --
+// Element a of a line-interleaved LDS buffer (C lines interleaved, element
+// stride C) is stored at a + C * (a / (16 C)): one pad slot group every 16
+// elements per line keeps strided butterfly writes on distinct banks.
+template <int C>
+__device__ __forceinline__ unsigned lds_pad(unsigned a) {
+  return a + C * (a / (16u * C));
+}
+template <int C, int N>
+struct LdsSize {
+  static constexpr int value = C * N + C * ((C * N) / (16 * C)) + C;
+};
+
+// ------------------------------------------------- Stockham FFT of a line --
+// A line of N = T * E points is spread over T threads; thread b holds
+// x[b + T k] in v[k], k < E, before and after the transform.  Pass s has
+// radix R and sub-length L (product of the earlier radices); thread b runs
+// the E/R butterflies beta = b + T q, q < E/R, reading x[beta + (N/R) m]
+// (= v[q + (E/R) m]), applying w_{LR}^(j m) with j = beta mod L, and writing
+// y[(beta - j) R + j + L m].  After the last pass every output lands back in
+// its own thread's slot, so only the passes before it go through LDS.
+// TWM selects how the twiddles w^(j m), m < R, are obtained: 0 = one table
+// load each (exactly rounded values), 1 = one table load of w^j and products
+// of at most four factors for the rest (fewer loads and registers in flight).
+template <int N, int E, int R, int L, bool INV, int TWM>
+__device__ __forceinline__ void stockham_compute(float2 (&v)[E], int b, const float2* __restrict__ tw) {
+  constexpr int Q = E / R;
+  constexpr int T = N / E;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    float2 a[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) a[m] = v[q + Q * m];
+    if constexpr (L > 1) {
+      const int beta = b + T * q;
+      const int j = beta % L;
+      constexpr int step = N / (L * R);
+      if constexpr (TWM == 0) {
+#pragma unroll
+      for (int m = 1; m < R; ++m) {
+        float2 w = tw[j * m * step];
+        a[m] = INV ? cmulc(a[m], w) : cmul(a[m], w);
+      }
+      } else {
+      // powers of w1 = w^j with multiplication depth <= 4
+      float2 w[R];
+      w[1] = tw[j * step];
+      if (INV) w[1].y = -w[1].y;
+#pragma unroll
+      for (int m = 2; m < R; ++m) {
+        const int hi = 1 << (31 - __builtin_clz(m));  // highest power of two <= m
+        w[m] = (m == hi) ? cmul(w[m / 2], w[m / 2]) : cmul(w[hi], w[m - hi]);
+      }
+#pragma unroll
+      for (int m = 1; m < R; ++m) a[m] = cmul(a[m], w[m]);
+      }
+    }
+    dft_reg<R, INV>(a);
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[q + Q * m] = a[m];
+  }
+}
+
+template <int N, int E, int R, int L, int C>
+__device__ __forceinline__ void stockham_exchange(float2 (&v)[E], int b, int c, float2* lds) {
+  constexpr int Q = E / R;
+  constexpr int T = N / E;
+  // Writes.  When R divides 16 (first pass) or L is a multiple of 16, the
+  // padded addresses of one butterfly's R outputs differ by compile-time
+  // constants, which the LDS instructions take as immediate offsets.
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int beta = b + T * q;
+    if constexpr (L == 1 && 16 % R == 0) {
+      const unsigned off = lds_pad<C>((unsigned)(beta * R * C + c));
+      __builtin_assume(off < 32768u);
+      float2* p = lds + off;
+#pragma unroll
+      for (int m = 0; m < R; ++m) p[m * C] = v[q + Q * m];
+    } else if constexpr (L % 16 == 0) {
+      const int j = beta % L;
+      const unsigned off = lds_pad<C>((unsigned)(((beta - j) * R + j) * C + c));
+      __builtin_assume(off < 32768u);
+      float2* p = lds + off;
+      constexpr int step = L * C + L * C / 16;
+#pragma unroll
+      for (int m = 0; m < R; ++m) p[m * step] = v[q + Q * m];
+    } else {
+      const int j = beta % L;
+      const int base = (beta - j) * R + j;
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[lds_pad<C>((base + L * m) * C + c)] = v[q + Q * m];
+    }
+  }
+  __syncthreads();
+  // Reads of x[b + T k]: constant stride when T is a multiple of 16.
+  if constexpr (T % 16 == 0) {
+    const unsigned off = lds_pad<C>((unsigned)(b * C + c));
+    __builtin_assume(off < 32768u);
+    const float2* p = lds + off;
+    constexpr int step = T * C + T * C / 16;
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = p[k * step];
+  } else {
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = lds[lds_pad<C>((b + T * k) * C + c)];
+  }
+  __syncthreads();
+}
+
+template <int N, bool INV, int C, int TWM, int S = 0>
+__device__ __forceinline__ void fft_line(float2 (&v)[Plan<N>::E], int b, int c, float2* lds,
+                                         const float2* __restrict__ tw) {
+  using P = Plan<N>;
+  if constexpr (S < P::P) {
+    constexpr int R = P::radix(S);
+    constexpr int L = P::sub(S);
+    __builtin_amdgcn_sched_barrier(0);
+    stockham_compute<N, P::E, R, L, INV, TWM>(v, b, tw);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (S + 1 < P::P) stockham_exchange<N, P::E, R, L, C>(v, b, c, lds);
+    fft_line<N, INV, C, TWM, S + 1>(v, b, c, lds, tw);
+  }
+}
+
+// --------------------------------------------------------- phase screens --
+// Per-Doppler-bin coefficient pairs (double2) and per-range-column pairs:
+//   rowc1[k] = (a1, d1):  Phi1 turns = a1 (dtau_j - d1)^2
+//   rowc3[k] = (D, b3):   Phi3 turns = D P_j + b3 dtau_j^2
+//   rowc2[k] = (a2, b2):  Phi2 turns = (a2 nu + b2) nu, nu = signed range bin
+//   colc[j]  = (P_j, dtau_j), P_j = fc tau_j, dtau_j = (j - N_r/2)/fs
+__device__ __forceinline__ double phi1_turns(double2 rc, double dtau) {
+  double u = dtau - rc.y;
+  return rc.x * (u * u);
+}
+__device__ __forceinline__ double phi3_turns(double2 rc, double2 cc) {
+  return fma(rc.x, cc.x, rc.y * (cc.y * cc.y));
+}
+__device__ __forceinline__ double phi2_turns(double2 rc, double nu) {
+  return fma(rc.x, nu, rc.y) * nu;
+}
+
+// ------------------------------------------------------- buffer access --
+// Global arrays are read and written through buffer resources: the
+// per-lane byte offset sits in one VGPR and the wave-uniform part (row
+// stride times element slot) in an SGPR, so no 64-bit per-lane addresses are
+// kept live, and accesses past num_records read 0 / are dropped.
+struct Buf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ Buf(const void* p, uint32_t bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
+  __device__ __forceinline__ float2 f2(uint32_t voff, uint32_t soff) const {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+  __device__ __forceinline__ double2 d2(uint32_t voff, uint32_t soff) const {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  }
+  __device__ __forceinline__ uint32_t u32(uint32_t voff, uint32_t soff) const {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+  }
+  __device__ __forceinline__ void st(float2 v, uint32_t voff, uint32_t soff) const {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
+  }
+};
+
+__device__ __forceinline__ uint32_t clamp_bytes(size_t n) {
+  return n > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)n;
+}
+
+// ----------------------------------------------------------- reductions --
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Block-wide sum of one float per thread (result valid in thread 0).
+template <int NT>
+__device__ __forceinline__ float block_sum(float x, float* red) {
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = x;
+  __syncthreads();
+  float s = 0.f;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+  }
+  return s;
+}
+
+// Partial written by every block; the last block to finish sums the partials
+// in block order (FP64) and stores the total, so the result does not depend
+// on completion order.  counter is reset for the next use.
+__device__ __forceinline__ void finish_partials(float part, float* partials, unsigned* counter,
+                                                float* out, unsigned* status, int nblocks) {
+  __shared__ int is_last;
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = part;
+    __threadfence();
+    unsigned done = atomicAdd(counter, 1u);
+    is_last = (done == (unsigned)(nblocks - 1));
+  }
+  __syncthreads();
+  if (is_last) {
+    __threadfence();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int i = 0; i < nblocks; ++i) s += (double)partials[i];
+      float f = (float)s;
+      if (out) out[0] = f;
+      if (!isfinite(s)) atomicOr(status, 1u);
+      atomicExch(counter, 0u);
+    }
+  }
+}
+
+}  // namespace cssar

@@ -1,0 +1,219 @@
+"""Thin ctypes binding of libcssar.so (include/cssar.h).
+
+Argument marshalling only: every step of G, G^H and the iterative
+thresholding runs in the library's HIP kernels.  Torch supplies device
+memory (complex64 CUDA/HIP tensors) and the current stream.  The library
+must have been built (``__graft_entry__.build()`` or
+``python paper_1302_3120_amd/build.py``); there is no fallback path.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcssar.so")
+
+OK, EINVAL, EUNSUPPORTED, EHIP, ENONFINITE, ENOMEM = 0, -1, -2, -3, -4, -5
+_ERRORS = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", EHIP: "EHIP",
+           ENONFINITE: "ENONFINITE", ENOMEM: "ENOMEM"}
+
+SYMBOLS = (
+    "cssar_make_operator", "cssar_destroy_operator", "cssar_workspace_size",
+    "cssar_apply_G", "cssar_apply_GH", "cssar_pack_mask", "cssar_ita_solve",
+    "cssar_sync_status", "cssar_last_error", "cssar_supported_length",
+    "cssar_plan_info", "cssar_profile_enable", "cssar_profile_read",
+)
+
+PROFILE_KINDS = ("row_M", "row_G", "col_fwd_phi1", "col_fwd_phi3c", "col_inv_phi1c",
+                 "col_inv_phi3", "col_update_threshold", "col_residual")
+
+
+class CssarError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("fc", ctypes.c_double), ("Kr", ctypes.c_double),
+                ("Tp", ctypes.c_double), ("fs", ctypes.c_double),
+                ("prf", ctypes.c_double), ("v", ctypes.c_double),
+                ("r_ref", ctypes.c_double), ("ba", ctypes.c_double),
+                ("f_dc", ctypes.c_double), ("src", ctypes.c_int)]
+
+    @classmethod
+    def from_dict(cls, d):
+        return cls(float(d["fc"]), float(d["Kr"]), float(d.get("Tp", 0.0)),
+                   float(d["fs"]), float(d["prf"]), float(d["v"]),
+                   float(d["r_ref"]), float(d.get("ba", 0.0)),
+                   float(d.get("f_dc", 0.0)), int(d.get("src", 1)))
+
+
+_lib = None
+
+
+def lib():
+    """Load libcssar.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, f = ctypes.c_void_p, ctypes.c_int, ctypes.c_float
+        L.cssar_make_operator.argtypes = [ctypes.POINTER(Params), i, i, ctypes.POINTER(vp)]
+        L.cssar_destroy_operator.argtypes = [vp]
+        L.cssar_workspace_size.argtypes = [vp, i]
+        L.cssar_workspace_size.restype = ctypes.c_size_t
+        L.cssar_apply_G.argtypes = [vp, vp, vp, vp, vp]
+        L.cssar_apply_GH.argtypes = [vp, vp, vp, vp, vp]
+        L.cssar_pack_mask.argtypes = [vp, vp, vp, vp]
+        L.cssar_ita_solve.argtypes = [vp, vp, vp, f, i, vp, vp, vp, vp]
+        L.cssar_sync_status.argtypes = [vp, vp]
+        L.cssar_last_error.restype = ctypes.c_char_p
+        L.cssar_supported_length.argtypes = [i]
+        L.cssar_plan_info.argtypes = [i, ctypes.POINTER(i), ctypes.POINTER(i),
+                                      ctypes.POINTER(i * 8)]
+        L.cssar_profile_enable.argtypes = [vp, i]
+        L.cssar_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double * 8),
+                                         ctypes.POINTER(ctypes.c_long * 8)]
+        for name in ("cssar_make_operator", "cssar_destroy_operator", "cssar_apply_G",
+                     "cssar_apply_GH", "cssar_pack_mask", "cssar_ita_solve",
+                     "cssar_sync_status", "cssar_supported_length", "cssar_plan_info",
+                     "cssar_profile_enable", "cssar_profile_read"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise CssarError(rc, lib().cssar_last_error().decode())
+    return rc
+
+
+def supported_length(n):
+    return bool(lib().cssar_supported_length(int(n)))
+
+
+def plan_info(n):
+    """(elements per thread, radices) of the FFT plan of a length."""
+    e, p = ctypes.c_int(), ctypes.c_int()
+    r = (ctypes.c_int * 8)()
+    _check(lib().cssar_plan_info(int(n), ctypes.byref(e), ctypes.byref(p), ctypes.byref(r)))
+    return e.value, [r[i] for i in range(p.value)]
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Operator:
+    """Approximated observation G and its adjoint G^H = M on an
+    N_a x N_r grid (the handle of cssar_make_operator)."""
+
+    def __init__(self, params, shape):
+        self.shape = (int(shape[0]), int(shape[1]))
+        self.params = dict(params)
+        self._p = Params.from_dict(params)
+        h = ctypes.c_void_p()
+        _check(lib().cssar_make_operator(ctypes.byref(self._p), self.shape[0],
+                                         self.shape[1], ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cssar_destroy_operator(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_size(self, mode):
+        return int(lib().cssar_workspace_size(self._h, int(mode)))
+
+    def _arr(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.complex64:
+            raise TypeError(f"{name} must be a complex64 tensor")
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be on the GPU")
+        if tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {self.shape}")
+        return t
+
+    def apply_G(self, x, out=None):
+        """y = G x."""
+        x = self._arr(x, "x")
+        out = torch.empty_like(x) if out is None else self._arr(out, "out")
+        _check(lib().cssar_apply_G(self._h, _ptr(x), _ptr(out), None, _stream()))
+        return out
+
+    def apply_GH(self, y, out=None):
+        """x = G^H y = M y (the focusing chain)."""
+        y = self._arr(y, "y")
+        out = torch.empty_like(y) if out is None else self._arr(out, "out")
+        _check(lib().cssar_apply_GH(self._h, _ptr(y), _ptr(out), None, _stream()))
+        return out
+
+    def pack_mask(self, mask):
+        """Pack a bool/uint8 N_a x N_r mask into the solver's bit layout."""
+        if mask.dtype not in (torch.bool, torch.uint8) or not mask.is_cuda:
+            raise TypeError("mask must be a bool or uint8 GPU tensor")
+        if tuple(mask.shape) != self.shape or not mask.is_contiguous():
+            raise ValueError(f"mask must be contiguous with shape {self.shape}")
+        n = self.shape[0] * self.shape[1]
+        bits = torch.empty((n + 31) // 32, dtype=torch.int32, device=mask.device)
+        _check(lib().cssar_pack_mask(self._h, _ptr(mask), _ptr(bits), _stream()))
+        return bits
+
+    def workspace(self, mode, device=None):
+        nbytes = self.workspace_size(mode)
+        return torch.empty(max(nbytes, 8), dtype=torch.uint8, device=device or "cuda")
+
+    def ita_solve(self, y, mask_bits, lam, iters, out=None, ws=None, resid=False):
+        """Iterative thresholding (eq. (th2d) / Algorithm 1), X^(0) = 0.
+        Returns X^(iters), and the residual norms ||R^(t)||^2 if resid."""
+        y = self._arr(y, "y")
+        if mask_bits.dtype != torch.int32 or not mask_bits.is_cuda:
+            raise TypeError("mask_bits must come from pack_mask")
+        out = torch.empty_like(y) if out is None else self._arr(out, "out")
+        ws = self.workspace(1, y.device) if ws is None else ws
+        if ws.numel() * ws.element_size() < self.workspace_size(1):
+            raise ValueError("workspace too small")
+        hist = torch.empty(int(iters), dtype=torch.float32, device=y.device) if resid else None
+        _check(lib().cssar_ita_solve(self._h, _ptr(y), _ptr(mask_bits), float(lam),
+                                     int(iters), _ptr(out),
+                                     _ptr(hist) if hist is not None else None,
+                                     _ptr(ws), _stream()))
+        return (out, hist) if resid else out
+
+    def sync_status(self):
+        _check(lib().cssar_sync_status(self._h, _stream()))
+
+    def profile(self, on):
+        """Enable/disable per-launch HIP event timing of the pass kernels."""
+        _check(lib().cssar_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """{kind: (total ms, launches)} since the last read (waits for the events)."""
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_long * 8)()
+        _check(lib().cssar_profile_read(self._h, ctypes.byref(ms), ctypes.byref(cnt)))
+        return {PROFILE_KINDS[k]: (ms[k], cnt[k]) for k in range(8) if cnt[k]}
+
+
+def make_operator(params, shape):
+    return Operator(params, shape)
