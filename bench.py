@@ -23,8 +23,7 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes per pixel for each pass kind (one read or write of a
 # complex64 array = 8 B/pixel; the packed mask = 1/8 B/pixel).
 PASS_BYTES = {
-    "row_M": 16.0, "row_G": 16.0,
-    "col_fwd_phi1": 16.0, "col_fwd_phi3c": 16.0, "col_inv_phi1c": 16.0, "col_inv_phi3": 16.0,
+    "row_M": 16.0, "row_G": 16.0, "col_fwd": 16.125, "col_inv": 16.0,
     "col_update_threshold": 24.0, "col_residual": 24.125,
 }
 ITER_BYTES = 80.125  # per pixel per ITA iteration: row G, col R, row M, col A

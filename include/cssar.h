@@ -87,22 +87,27 @@ int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** ou
 /* Release an operator and its tables (NULL is accepted). */
 int cssar_destroy_operator(cssar_op* op);
 
-/* Workspace bytes the caller must provide:
- *   mode 0: cssar_apply_G / cssar_apply_GH   (0 bytes: outputs double as scratch)
- *   mode 1: cssar_ita_solve                  (one N_a x N_r complex64 array)
- * Returns 0 for a NULL operator or an unknown mode. */
+/* Workspace bytes the caller must provide (device memory, 256-byte aligned
+ * start; contents need not be initialised and are clobbered):
+ *   mode 0: cssar_apply_G / cssar_apply_GH   (one array in the blocked layout)
+ *   mode 1: cssar_ita_solve                  (three arrays in the blocked layout)
+ * The blocked layout holds 4 x 4 blocks of 128 bytes with a 128-byte pad per
+ * block row: (N_a/4) (32 N_r + 128) bytes per array.  Returns 0 for a NULL
+ * operator or an unknown mode. */
 size_t cssar_workspace_size(const cssar_op* op, int mode);
 
 /* y_out = G x (approximated observation, Section III.B).  x and y_out are
- * N_a x N_r complex64; ws may be NULL.  y_out must not alias x. */
+ * N_a x N_r complex64 (row-major); ws: cssar_workspace_size(op, 0) bytes.
+ * No two of x, y_out, ws may alias. */
 int cssar_apply_G(cssar_op* op, const void* x, void* y_out, void* ws, void* stream);
 
 /* x_out = G^H y = M y (focusing chain, Theorem 1).  Same layout rules. */
 int cssar_apply_GH(cssar_op* op, const void* y, void* x_out, void* ws, void* stream);
 
 /* Pack a row-major N_a x N_r byte mask (nonzero = sampled) into the bit
- * layout the solver reads: bit (i*N_r + j) of the 32-bit word array, LSB
- * first.  mask_bits must hold ceil(N_a*N_r/32) words. */
+ * layout the solver reads: 32-bit words, LSB first, bit e set for the
+ * element with blocked index e = ((i/4) (N_r/4) + j/4) 16 + (i%4) 4 + j%4.
+ * mask_bits must hold ceil(N_a N_r / 32) words. */
 int cssar_pack_mask(const cssar_op* op, const void* mask_bytes, void* mask_bits, void* stream);
 
 /* Iterative thresholding, eq. (th2d) / Algorithm 1:
@@ -111,7 +116,7 @@ int cssar_pack_mask(const cssar_op* op, const void* mask_bytes, void* mask_bits,
  * mask_bits: packed mask (cssar_pack_mask); lambda >= 0; iters >= 1;
  * x_out: N_a x N_r complex64 result X^(iters);
  * resid_hist: NULL or a device array of iters floats receiving ||R^(t)||^2;
- * ws: cssar_workspace_size(op, 1) bytes.  x_out must not alias y or ws. */
+ * ws: cssar_workspace_size(op, 1) bytes.  No two of y, x_out, ws may alias. */
 int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda,
                     int iters, void* x_out, float* resid_hist, void* ws, void* stream);
 
@@ -126,10 +131,10 @@ const char* cssar_last_error(void);
  * an operator enqueues is bracketed by two HIP events on its stream.
  * cssar_profile_read waits for those events, returns the summed elapsed
  * milliseconds and launch counts per pass kind, and forgets them.  Kinds:
- * 0 row pass with Phi2 (inside M), 1 row pass with Phi2* (inside G),
- * 2 column forward transform + Phi1, 3 column forward + Phi3*, 4 column
- * Phi1* + inverse, 5 column Phi3 + inverse, 6 column update/threshold pass,
- * 7 column residual pass. */
+ * 0 row pass of M (Phi1, range FFT, Phi2, inverse, Phi3), 1 row pass of G
+ * (conjugate screens, reverse order), 2 column forward azimuth FFT (with
+ * optional mask and residual norm), 3 column inverse azimuth FFT, 4 column
+ * update + soft-threshold pass, 5 column residual pass; 6 and 7 unused. */
 #define CSSAR_PROFILE_KINDS 8
 int cssar_profile_enable(cssar_op* op, int on);
 int cssar_profile_read(cssar_op* op, double* ms_sum, long* counts);

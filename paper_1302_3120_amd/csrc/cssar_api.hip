@@ -56,6 +56,8 @@ const KernelTable* table_for(int n) {
 
 int signed_bin(int k, int n) { return k < (n + 1) / 2 ? k : k - n; }
 
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
 }  // namespace
 
 struct cssar_op {
@@ -68,7 +70,6 @@ struct cssar_op {
   double2* rowc1 = nullptr;         // per Doppler bin: Phi1 (a1, d1)
   double2* rowc2 = nullptr;         //                  Phi2 (a2, b2)
   double2* rowc3 = nullptr;         //                  Phi3 (D, b3)
-  double2* colc = nullptr;          // per range column: (P_j, dtau_j)
   float2* tw_a = nullptr;           // w_{N_a}^k
   float2* tw_r = nullptr;           // w_{N_r}^k
   float* partials = nullptr;        // per-block partial sums
@@ -93,9 +94,10 @@ namespace {
 //   Phi1 = a1 (dtau - d1)^2, a1 = Km (1/D - 1) / 2, d1 = 2 r_ref (1/D - 1) / c
 //   Phi2 = (a2 nu + b2) nu,  a2 = D / (2 Km) (fs/N_r)^2, b2 = 2 r_ref (1/D - 1) / c (fs/N_r)
 //   Phi3 = D P_j + b3 dtau^2, b3 = -Km (1 - D) / (2 D^2), P_j = fc tau_j
+// with dtau = (j - N_r/2) / fs and tau_j = 2 r_ref / c + dtau (the kernels
+// expand Phi1 and Phi3 as polynomials in j - N_r/2).
 void build_coefficients(const cssar_params& p, int na, int nr, std::vector<double2>& r1,
-                        std::vector<double2>& r2, std::vector<double2>& r3,
-                        std::vector<double2>& cc) {
+                        std::vector<double2>& r2, std::vector<double2>& r3) {
   const double lam = kC / p.fc;
   const double df = p.fs / nr;
   r1.resize(na);
@@ -111,12 +113,6 @@ void build_coefficients(const cssar_params& p, int na, int nr, std::vector<doubl
     r1[k] = make_double2(0.5 * Km * invD1, 2.0 * p.r_ref * invD1 / kC);
     r2[k] = make_double2(0.5 * D / Km * df * df, 2.0 * p.r_ref * invD1 / kC * df);
     r3[k] = make_double2(D, -0.5 * Km * (1.0 - D) / (D * D));
-  }
-  cc.resize(nr);
-  for (int j = 0; j < nr; ++j) {
-    const double dtau = (j - nr / 2) / p.fs;
-    const double tau = 2.0 * p.r_ref / kC + dtau;
-    cc[j] = make_double2(p.fc * tau, dtau);
   }
 }
 
@@ -162,7 +158,6 @@ int grid_for(int work, int cus, int per_cu) {
 
 ColArgs col_args(const cssar_op* op) {
   ColArgs a{};
-  a.colc = op->colc;
   a.tw = op->tw_a;
   a.na = op->na;
   a.nr = op->nr;
@@ -178,11 +173,16 @@ RowArgs row_args(const cssar_op* op, const void* in, void* out, int conj) {
   RowArgs a{};
   a.in = (const float2*)in;
   a.out = (float2*)out;
+  a.rowc1 = op->rowc1;
   a.rowc2 = op->rowc2;
+  a.rowc3 = op->rowc3;
   a.tw = op->tw_r;
   a.na = op->na;
   a.conj = conj;
   a.scale = 1.0f / (float)op->nr;
+  a.inv_fs = 1.0 / op->p.fs;
+  a.fc_fs = op->p.fc / op->p.fs;
+  a.p_c = op->p.fc * 2.0 * op->p.r_ref / kC;
   return a;
 }
 
@@ -197,7 +197,7 @@ hipEvent_t take_event(cssar_op* op) {
   return e;
 }
 
-// Kind ids of cssar_profile_read: 0/1 row pass (Phi2 / Phi2*), 2 + column kernel id.
+// Kind ids of cssar_profile_read: 0/1 row pass (M / G chain), 2 + column kernel id.
 template <typename F>
 int timed(cssar_op* op, int kind, hipStream_t s, F&& launch) {
   hipEvent_t a = nullptr, b = nullptr;
@@ -253,8 +253,8 @@ int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** ou
   if (n_rg % ka->C != 0 || n_rg % 32 != 0)
     return fail(CSSAR_EUNSUPPORTED, "range length %d incompatible with the column tile", n_rg);
 
-  std::vector<double2> r1, r2, r3, cc;
-  build_coefficients(*p, n_az, n_rg, r1, r2, r3, cc);
+  std::vector<double2> r1, r2, r3;
+  build_coefficients(*p, n_az, n_rg, r1, r2, r3);
   for (int k = 0; k < n_az; ++k)
     if (!std::isfinite(r1[k].x) || !std::isfinite(r2[k].x) || !std::isfinite(r3[k].y))
       return fail(CSSAR_EINVAL, "parameters give non-finite phase coefficients");
@@ -277,15 +277,14 @@ int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** ou
     return cleanup(fail(CSSAR_EHIP, "cannot query the compute unit count"));
   const size_t rowb = sizeof(double2) * n_az;
   void* mem = nullptr;
-  const size_t total = 3 * rowb + sizeof(double2) * n_rg + sizeof(float2) * (n_az + n_rg) +
+  const size_t total = 3 * rowb + sizeof(float2) * (n_az + n_rg) +
                        sizeof(float) * kMaxPartials + 4 * sizeof(unsigned) + 1024;
   if (hipMalloc(&mem, total) != hipSuccess) return cleanup(fail(CSSAR_ENOMEM, "hipMalloc of %zu bytes failed", total));
   char* base = (char*)mem;
   op->rowc1 = (double2*)base;
   op->rowc2 = (double2*)(base + rowb);
   op->rowc3 = (double2*)(base + 2 * rowb);
-  op->colc = (double2*)(base + 3 * rowb);
-  op->tw_a = (float2*)((char*)op->colc + sizeof(double2) * n_rg);
+  op->tw_a = (float2*)(base + 3 * rowb);
   op->tw_r = op->tw_a + n_az;
   op->partials = (float*)(op->tw_r + n_rg);
   op->counter = (unsigned*)(op->partials + kMaxPartials);
@@ -293,7 +292,6 @@ int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** ou
   if (e == hipSuccess) e = hipMemcpy(op->rowc1, r1.data(), rowb, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(op->rowc2, r2.data(), rowb, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(op->rowc3, r3.data(), rowb, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(op->colc, cc.data(), sizeof(double2) * n_rg, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(op->tw_a, ta.data(), sizeof(float2) * n_az, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(op->tw_r, tr.data(), sizeof(float2) * n_rg, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(op->counter, 0, 4 * sizeof(unsigned));
@@ -324,54 +322,49 @@ int cssar_destroy_operator(cssar_op* op) {
 
 size_t cssar_workspace_size(const cssar_op* op, int mode) {
   if (!op) return 0;
-  const size_t n = (size_t)op->na * op->nr * sizeof(float2);
+  const size_t blk = align256(b4_bytes(op->na, op->nr));
   switch (mode) {
     case 0:
-      return 0;
+      return blk;
     case 1:
-      return n;
+      return 3 * blk;
     default:
       return 0;
   }
 }
 
 int cssar_apply_GH(cssar_op* op, const void* y, void* x_out, void* ws, void* stream) {
-  (void)ws;
   int rc = check_op(op);
   if (rc) return rc;
-  if (!y || !x_out) return fail(CSSAR_EINVAL, "NULL array");
-  if (y == x_out) return fail(CSSAR_EINVAL, "output aliases input");
+  if (!y || !x_out || !ws) return fail(CSSAR_EINVAL, "NULL array or workspace");
+  if (y == x_out || ws == y || ws == x_out) return fail(CSSAR_EINVAL, "arrays must not alias");
   hipStream_t s = (hipStream_t)stream;
-  // x = F_eta^-1 [Phi3 o F_tau^-1 [Phi2 o F_tau [Phi1 o F_eta y]]], x_out as scratch
+  // x = F_eta^-1 [Phi3 o F_tau^-1 [Phi2 o F_tau [Phi1 o F_eta y]]]
   ColArgs a = col_args(op);
   a.in0 = (const float2*)y;
+  a.out = (float2*)ws;
+  if ((rc = launch_col(op, CK_FWD, a, s))) return rc;
+  if ((rc = launch_row(op, row_args(op, ws, ws, 0), s))) return rc;
+  a.in0 = (const float2*)ws;
   a.out = (float2*)x_out;
-  a.rowc = op->rowc1;
-  if ((rc = launch_col(op, CK_FWD1, a, s))) return rc;
-  if ((rc = launch_row(op, row_args(op, x_out, x_out, 0), s))) return rc;
-  a.in0 = (const float2*)x_out;
-  a.rowc = op->rowc3;
-  return launch_col(op, CK_INV3, a, s);
+  return launch_col(op, CK_INV, a, s);
 }
 
 int cssar_apply_G(cssar_op* op, const void* x, void* y_out, void* ws, void* stream) {
-  (void)ws;
   int rc = check_op(op);
   if (rc) return rc;
-  if (!x || !y_out) return fail(CSSAR_EINVAL, "NULL array");
-  if (x == y_out) return fail(CSSAR_EINVAL, "output aliases input");
+  if (!x || !y_out || !ws) return fail(CSSAR_EINVAL, "NULL array or workspace");
+  if (x == y_out || ws == x || ws == y_out) return fail(CSSAR_EINVAL, "arrays must not alias");
   hipStream_t s = (hipStream_t)stream;
   // y = F_eta^-1 [Phi1* o F_tau^-1 [Phi2* o F_tau [Phi3* o F_eta x]]]
   ColArgs a = col_args(op);
   a.in0 = (const float2*)x;
+  a.out = (float2*)ws;
+  if ((rc = launch_col(op, CK_FWD, a, s))) return rc;
+  if ((rc = launch_row(op, row_args(op, ws, ws, 1), s))) return rc;
+  a.in0 = (const float2*)ws;
   a.out = (float2*)y_out;
-  a.rowc = op->rowc3;
-  a.conj = 1;
-  if ((rc = launch_col(op, CK_FWD3, a, s))) return rc;
-  if ((rc = launch_row(op, row_args(op, y_out, y_out, 1), s))) return rc;
-  a.in0 = (const float2*)y_out;
-  a.rowc = op->rowc1;
-  return launch_col(op, CK_INV1, a, s);
+  return launch_col(op, CK_INV, a, s);
 }
 
 int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters,
@@ -383,39 +376,39 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
   if (!(lambda >= 0.0f) || !std::isfinite(lambda)) return fail(CSSAR_EINVAL, "lambda must be finite and >= 0");
   if (x_out == y || x_out == ws || ws == y) return fail(CSSAR_EINVAL, "x_out, y and ws must not alias");
   hipStream_t s = (hipStream_t)stream;
-  float2* X = (float2*)x_out;  // holds Xt = Phi3* o F_eta X between iterations
-  float2* P = (float2*)ws;     // Wg / R / W, updated in place by each pass
+  const size_t blk = align256(b4_bytes(op->na, op->nr));
+  float2* X = (float2*)ws;                       // Xt = F_eta X (blocked layout)
+  float2* P = (float2*)((char*)ws + blk);        // F_eta G X, F_eta R, F_eta M R (in place)
+  float2* Y = (float2*)((char*)ws + 2 * blk);    // m o y (blocked layout)
   ColArgs a = col_args(op);
-  a.y = (const float2*)y;
+  a.y = Y;
   a.mask = (const uint32_t*)mask_bits;
   a.sigma = lambda * a.mu;
   for (int t = 0; t < iters; ++t) {
     const bool last = t == iters - 1;
     a.hist_out = resid_hist ? resid_hist + t : nullptr;
     if (t == 0) {
-      // R(0) = m o y (G X(0) = 0): P = Phi1 o F_eta R
+      // R(0) = m o y (G X(0) = 0): P = F_eta R, and keep m o y for later residuals
       ColArgs f = a;
       f.in0 = (const float2*)y;
       f.out = P;
-      f.rowc = op->rowc1;
-      f.flags = 1;
-      if ((rc = launch_col(op, CK_FWD1, f, s))) return rc;
+      f.out2 = Y;
+      f.flags = 1 | 4;
+      if ((rc = launch_col(op, CK_FWD, f, s))) return rc;
     } else {
-      // Wg = F_tau^-1 Phi2* F_tau Xt ; then R = m o (y - G X), P = Phi1 o F_eta R
+      // P = F_eta G X (row chain of G on Xt); then R = m o y - m o G X, P = F_eta R
       if ((rc = launch_row(op, row_args(op, X, P, 1), s))) return rc;
       ColArgs r = a;
       r.in0 = P;
       r.out = P;
-      r.rowc = op->rowc1;
       if ((rc = launch_col(op, CK_R, r, s))) return rc;
     }
-    // W = F_tau^-1 Phi2 F_tau P  (so that F_eta M R = Phi3 o W)
+    // P = F_eta M R (row chain of M)
     if ((rc = launch_row(op, row_args(op, P, P, 0), s))) return rc;
     ColArgs u = a;
     u.in0 = X;
     u.in1 = P;
-    u.out = X;
-    u.rowc = op->rowc3;
+    u.out = last ? (float2*)x_out : X;
     u.flags = (t == 0 ? 1 : 0) | (last ? 2 : 0);
     u.hist_out = nullptr;
     if ((rc = launch_col(op, CK_A, u, s))) return rc;
@@ -471,15 +464,19 @@ int cssar_sync_status(cssar_op* op, void* stream) {
 
 // ------------------------------------------------------------ mask packing --
 namespace {
-__global__ void pack_mask_kernel(const unsigned char* __restrict__ m, uint32_t* __restrict__ bits, size_t n) {
+// Word w of the packed mask holds blocked element indices 32 w .. 32 w + 31:
+// e = ((i/4) (N_r/4) + j/4) 16 + (i%4) 4 + j%4, i.e. two 4 x 4 blocks.
+__global__ void pack_mask_kernel(const unsigned char* __restrict__ m, uint32_t* __restrict__ bits, int na, int nr) {
   const size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t nw = (n + 31) / 32;
+  const size_t nw = ((size_t)na * nr + 31) / 32;
   if (w >= nw) return;
   uint32_t word = 0;
-  const size_t base = w * 32;
-  for (int i = 0; i < 32; ++i) {
-    const size_t idx = base + i;
-    if (idx < n && m[idx]) word |= 1u << i;
+  for (int q = 0; q < 32; ++q) {
+    const size_t e = w * 32 + q;
+    const size_t blk = e >> 4;
+    const size_t bi = blk / (size_t)(nr / 4), bj = blk % (size_t)(nr / 4);
+    const size_t i = bi * 4 + ((e >> 2) & 3), j = bj * 4 + (e & 3);
+    if (i < (size_t)na && m[i * nr + j]) word |= 1u << q;
   }
   bits[w] = word;
 }
@@ -494,7 +491,7 @@ extern "C" int cssar_pack_mask(const cssar_op* op, const void* mask_bytes, void*
   const int block = 256;
   const unsigned grid = (unsigned)((nw + block - 1) / block);
   hipLaunchKernelGGL(pack_mask_kernel, dim3(grid), dim3(block), 0, (hipStream_t)stream,
-                     (const unsigned char*)mask_bytes, (uint32_t*)mask_bits, n);
+                     (const unsigned char*)mask_bytes, (uint32_t*)mask_bits, op->na, op->nr);
   HIP_TRY(hipGetLastError());
   return CSSAR_OK;
 }

@@ -176,29 +176,6 @@ __device__ __forceinline__ float2 cis_quadrant(float r, int q) {
   return make_float2(cc, ss);
 }
 
-// Reduced phase: remainder r (|r| <= 1/8 turn, FP32) and quarter-turn count q.
-struct Turns {
-  float r;
-  int q;
-};
-
-// Reduce an FP64 phase in turns modulo 1 and to the nearest quarter turn in
-// FP64; only the remainder is rounded to FP32.
-__device__ __forceinline__ Turns reduce_turns(double t) {
-  double f = t - floor(t);
-  double q = rint(4.0 * f);
-  Turns o;
-  o.r = (float)fma(q, -0.25, f);
-  o.q = (int)q;
-  return o;
-}
-
-// exp(2 pi i t) for an FP64 phase in turns.
-__device__ __forceinline__ float2 cis_turns(double t) {
-  Turns u = reduce_turns(t);
-  return cis_quadrant(u.r, u.q);
-}
-
 // ------------------------------------------------------------ LDS layout --
 // Element a of a line-interleaved LDS buffer (C lines interleaved, element
 // stride C) is stored at a + C * (a / (16 C)): one pad slot group every 16
@@ -325,20 +302,35 @@ __device__ __forceinline__ void fft_line(float2 (&v)[Plan<N>::E], int b, int c, 
 }
 
 // --------------------------------------------------------- phase screens --
-// Per-Doppler-bin coefficient pairs (double2) and per-range-column pairs:
-//   rowc1[k] = (a1, d1):  Phi1 turns = a1 (dtau_j - d1)^2
-//   rowc3[k] = (D, b3):   Phi3 turns = D P_j + b3 dtau_j^2
-//   rowc2[k] = (a2, b2):  Phi2 turns = (a2 nu + b2) nu, nu = signed range bin
-//   colc[j]  = (P_j, dtau_j), P_j = fc tau_j, dtau_j = (j - N_r/2)/fs
-__device__ __forceinline__ double phi1_turns(double2 rc, double dtau) {
-  double u = dtau - rc.y;
-  return rc.x * (u * u);
+// Within one range line (fixed Doppler bin) each phase screen is a quadratic
+// polynomial in the element's offset, in turns.  Thread b holds offsets
+// o = b + T k' (k' a compile-time integer per register slot), so the phase of
+// slot k' is A + B k' + C k'^2 with A, B (per thread) and C (per line)
+// reduced modulo 1 in FP64 once; per element only two FP64 FMAs and the
+// quarter-turn reduction remain, and the remainder is rounded to FP32.
+struct Quad {
+  double A, B, C;
+};
+
+__device__ __forceinline__ double frac1(double x) { return x - floor(x); }
+
+// Polynomial p0 + p1 o + p2 o^2 over o = b + T k': coefficients in k'.
+__device__ __forceinline__ Quad quad_in_slot(double p0, double p1, double p2, int b, int T) {
+  const double bb = (double)b, tt = (double)T;
+  Quad q;
+  q.A = frac1(fma(fma(p2, bb, p1), bb, p0));
+  q.B = frac1(fma(2.0 * p2 * bb, tt, p1 * tt));
+  q.C = frac1(p2 * tt * tt);
+  return q;
 }
-__device__ __forceinline__ double phi3_turns(double2 rc, double2 cc) {
-  return fma(rc.x, cc.x, rc.y * (cc.y * cc.y));
-}
-__device__ __forceinline__ double phi2_turns(double2 rc, double nu) {
-  return fma(rc.x, nu, rc.y) * nu;
+
+// exp(2 pi i (A + B k + C k^2)) for a small integer k.
+__device__ __forceinline__ float2 cis_quad(const Quad& q, int k) {
+  const double dk = (double)k;
+  const double t4 = 4.0 * fma(fma(q.C, dk, q.B), dk, q.A);  // quarter turns
+  const double qn = rint(t4);
+  const float r = (float)((t4 - qn) * 0.25);
+  return cis_quadrant(r, (int)qn);
 }
 
 // ------------------------------------------------------- buffer access --

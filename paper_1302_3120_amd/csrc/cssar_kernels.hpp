@@ -1,49 +1,83 @@
-// Fused pass kernels.  A pass reads whole lines of the N_a x N_r array,
+// Fused pass kernels.  A pass reads whole lines of an N_a x N_r array,
 // transforms them in registers/LDS and writes them back (in place allowed):
 //
-//   row pass  (line = one range line, contiguous):  F_tau -> x Phi2 (or
-//             Phi2*) / N_r -> F_tau^-1.  The middle of M (resp. G).
-//   col pass  (tile = C adjacent azimuth columns, stride N_r):
-//     FWD<ph>: [m o y, ||.||^2]  -> F_eta -> x Phi_ph (or conj)
-//     INV<ph>: x Phi_ph (or conj) / N_a -> F_eta^-1
-//     A:       V = F_eta^-1[Phi3 (Xt + mu W)] / N_a -> X+ = S_sigma(V)
-//              -> either X+ (last iteration) or Xt+ = Phi3* F_eta X+
-//     R:       GX = F_eta^-1[Phi1* Wg] / N_a -> R = m o (y - GX), ||R||^2
-//              -> Phi1 F_eta R
+//   row pass M (line = one range line at Doppler bin i):
+//       x Phi1 -> F_tau -> x Phi2 / N_r -> F_tau^-1 -> x Phi3
+//   row pass G:  x Phi3* -> F_tau -> x Phi2* / N_r -> F_tau^-1 -> x Phi1*
+//   col passes (tile = C adjacent azimuth columns):
+//     FWD:  [m o y, ||.||^2, copy of m o y] -> F_eta
+//     INV:  / N_a -> F_eta^-1
+//     A:    V = F_eta^-1[Xt + mu Z] / N_a -> X+ = S_sigma(V) -> F_eta X+ (or X+)
+//     R:    GX = F_eta^-1[W] / N_a -> R = m o y - m o GX, ||R||^2 -> F_eta R
 //
-// The ITA keeps the iterate as Xt = Phi3* o F_eta X (azimuth spectrum with the
-// azimuth-compression phase removed) so that every pass evaluates exactly one
-// phase screen per element; see the operator schedule in cssar_api.hip.
+// All three phase screens are evaluated in the row passes, where each is a
+// quadratic polynomial in the element's offset along the line.
+//
+// Memory layouts.  Arrays handed over by the caller are row-major ("RM":
+// element (i, j) at byte 8 (i N_r + j)).  Arrays that stay inside a solve or
+// an operator application use the blocked layout "B4": 4 x 4 blocks of 128
+// bytes, element (i, j) at byte (i/4) S + (j/4) 128 + (i%4) 32 + (j%4) 8, with
+// a block-row stride S = 32 N_r + 128.  A row pass that handles four rows and
+// a column pass that handles four columns both move whole 128-byte blocks,
+// and the 128-byte pad per block row spreads a column's blocks over the HBM
+// channels (without it a column walks a power-of-two stride).
 #pragma once
 
 #include "cssar_device.hpp"
 
 namespace cssar {
 
+enum Layout { RM = 0, B4 = 1 };
+
+__host__ __device__ constexpr uint32_t b4_stride(int nr) { return 32u * (uint32_t)nr + 128u; }
+__host__ __device__ constexpr size_t b4_bytes(int na, int nr) { return (size_t)(na / 4) * b4_stride(nr); }
+
+// Byte offset of element (i, j), i = b + T k, as a per-lane part (k = 0) and
+// a wave-uniform step per k (T a multiple of 4).
+struct Addr {
+  uint32_t voff, kstep;
+};
+__device__ __forceinline__ Addr col_addr(int layout, int b, int j, int T, int nr) {
+  Addr a;
+  if (layout == B4) {
+    const uint32_t S = b4_stride(nr);
+    a.voff = (uint32_t)(b >> 2) * S + (uint32_t)(j >> 2) * 128u + (uint32_t)(b & 3) * 32u + (uint32_t)(j & 3) * 8u;
+    a.kstep = (uint32_t)(T / 4) * S;
+  } else {
+    a.voff = ((uint32_t)b * nr + j) * 8u;
+    a.kstep = (uint32_t)T * nr * 8u;
+  }
+  return a;
+}
+
 struct RowArgs {
-  const float2* in;
-  float2* out;
-  const double2* rowc2;  // Phi2 coefficients per Doppler bin (row)
+  const float2* in;      // B4
+  float2* out;           // B4
+  const double2* rowc1;  // per Doppler bin: Phi1 (a1, d1)
+  const double2* rowc2;  //                  Phi2 (a2, b2)
+  const double2* rowc3;  //                  Phi3 (D, b3)
   const float2* tw;      // w_N^k, N = N_r
   int na;
-  int conj;              // 1: Phi2* (operator G)
+  int conj;              // 0: M (Phi1, Phi2, Phi3); 1: G (Phi3*, Phi2*, Phi1*)
   float scale;           // 1 / N_r
+  double inv_fs;         // 1 / fs
+  double fc_fs;          // fc / fs
+  double p_c;            // fc * 2 r_ref / c (Phi3 turns per unit D at the reference range)
 };
 
 enum ColMode { COL_FWD = 0, COL_INV = 1, COL_A = 2, COL_R = 3 };
 
 struct ColArgs {
-  const float2* in0;     // FWD/INV: input; A: Xt (NULL on the first iteration); R: Wg
-  const float2* in1;     // A: W
-  const float2* y;       // R and masked FWD: raw data
-  const uint32_t* mask;  // R and masked FWD: packed sampling mask
-  float2* out;
-  const double2* rowc;   // Phi1 or Phi3 coefficients per Doppler bin
-  const double2* colc;   // (P_j, dtau_j) per range column
+  const float2* in0;     // FWD: input (RM); INV: input (B4); A: Xt (B4, NULL on the first iteration); R: W (B4)
+  const float2* in1;     // A: Z (B4)
+  const float2* y;       // R: m o y (B4)
+  const uint32_t* mask;  // packed sampling mask, bit = blocked element index
+  float2* out;           // FWD, R: B4; INV: RM; A: B4, or RM with flag 2
+  float2* out2;          // FWD with flag 4: copy of m o y (B4)
   const float2* tw;      // w_N^k, N = N_a
   int na, nr;
-  int conj;              // FWD/INV: multiply by the conjugate screen
-  int flags;             // FWD: 1 = mask the input and sum |.|^2; A: 1 = no Xt input, 2 = store X
+  int flags;             // FWD: 1 = mask the input and sum |.|^2, 4 = write out2;
+                         // A: 1 = no Xt input, 2 = store X (RM) instead of F_eta X (B4)
   float scale;           // 1 / N_a (inverse transforms)
   float mu, sigma;       // A: step and threshold lambda*mu
   float* partials;       // per-block partial sums of ||R||^2
@@ -52,20 +86,9 @@ struct ColArgs {
   unsigned* status;      // bit 0: non-finite residual
 };
 
-// Phase of element (i, j), i = b + T k: coefficients read at byte offset
-// b*16 (lane) + T*k*16 (uniform).
-template <int PH>
-__device__ __forceinline__ Turns col_turns(const Buf& rowc, uint32_t boff, uint32_t koff, double2 cc) {
-  const double2 rc = rowc.d2(boff, koff);
-  if constexpr (PH == 1)
-    return reduce_turns(phi1_turns(rc, cc.y));
-  else
-    return reduce_turns(phi3_turns(rc, cc));
-}
-
 // Elementwise work on the E register elements in chunks of CH, with
 // scheduling barriers between chunks so the compiler does not hoist every
-// coefficient load and FP64 phase evaluation at once (register pressure).
+// FP64 phase evaluation at once (register pressure).
 template <int E, int CH, typename F>
 __device__ __forceinline__ void chunked(F&& f) {
 #pragma unroll
@@ -76,21 +99,67 @@ __device__ __forceinline__ void chunked(F&& f) {
   }
 }
 
+// Range-Doppler screens as polynomials of the centred column offset
+// o = j - N_r/2 (dtau = o / fs):
+//   Phi1 turns = a1 (o/fs - d1)^2 = a1 d1^2 - 2 a1 d1 o/fs + a1 o^2/fs^2
+//   Phi3 turns = D (p_c + o fc/fs) + b3 o^2/fs^2
+// and the 2-D frequency screen of the signed range bin nu:
+//   Phi2 turns = b2 nu + a2 nu^2
+__device__ __forceinline__ Quad phi1_quad(double2 c, const RowArgs& a, int b, int T) {
+  const double f = a.inv_fs;
+  return quad_in_slot(c.x * c.y * c.y, -2.0 * c.x * c.y * f, c.x * f * f, b, T);
+}
+__device__ __forceinline__ Quad phi3_quad(double2 c, const RowArgs& a, int b, int T) {
+  const double f = a.inv_fs;
+  return quad_in_slot(c.x * a.p_c, c.x * a.fc_fs, c.y * f * f, b, T);
+}
+__device__ __forceinline__ Quad phi2_quad(double2 c, int b, int T) {
+  return quad_in_slot(0.0, c.y, c.x, b, T);
+}
+
+// v[k] *= exp(+-2 pi i phase(k')) * s, with k' = k - E/2 (column offset
+// screens) or the signed bin slot (frequency screen: k' = k or k - E).
+template <int E, bool FREQ>
+__device__ __forceinline__ void apply_quad(float2 (&v)[E], const Quad& q, bool conj, float s) {
+  chunked<E, 4>([&](int k) {
+    const int kk = FREQ ? (k < E / 2 ? k : k - E) : k - E / 2;
+    float2 p = cis_quad(q, kk);
+    p = make_float2(p.x * s, (conj ? -p.y : p.y) * s);
+    v[k] = cmul(v[k], p);
+  });
+}
+
+// Row pass (B4 in and out).  Thread t of a workgroup with LR = 4 G rows:
+// g = t / 4T picks the block row, and within it lane bits 0-1 give j % 4,
+// bits 2-3 the row in the block, the rest the block along the row, so the
+// 64 lanes of a wave read 4 consecutive 128-byte blocks.
 template <int N>
 __global__ __launch_bounds__(Plan<N>::RT, (Plan<N>::E <= 16 ? 4 : 2)) void row_pass_kernel(RowArgs a) {
   using P = Plan<N>;
   constexpr int E = P::E, T = P::T, LR = P::LR;
   constexpr int LS = LdsSize<1, N>::value;
+  constexpr int TW = 1;  // twiddle mode
   __shared__ float2 lds[LR * LS];
-  const int line = threadIdx.x / T;
-  const int b = threadIdx.x % T;
-  const uint32_t bytes = clamp_bytes((size_t)a.na * N * 8);
+  int line, b;
+  if constexpr (LR == 1) {
+    line = 0;
+    b = threadIdx.x;
+  } else {
+    const int g = threadIdx.x / (4 * T), t = threadIdx.x % (4 * T);
+    line = 4 * g + ((t >> 2) & 3);
+    b = (t & 3) | ((t >> 4) << 2);
+  }
+  const uint32_t S = b4_stride(N);
+  const uint32_t bytes = clamp_bytes(b4_bytes(a.na, N));
   const Buf in(a.in, bytes), out(a.out, bytes);
+  const bool conj = a.conj != 0;
   const int groups = (a.na + LR - 1) / LR;
-  for (int g = blockIdx.x; g < groups; g += gridDim.x) {
-    const int row = g * LR + line;
+  for (int gi = blockIdx.x; gi < groups; gi += gridDim.x) {
+    const int row = gi * LR + line;
     const bool active = row < a.na;
-    const uint32_t voff = ((uint32_t)(active ? row : 0) * N + b) * 8u;
+    const int rr = active ? row : 0;
+    const uint32_t voff = (uint32_t)(rr >> 2) * S + (uint32_t)(b >> 2) * 128u + (uint32_t)(rr & 3) * 32u +
+                          (uint32_t)(b & 3) * 8u;
     int lb = b;
     asm volatile("" : "+v"(lb));  // recompute LDS addresses per row (register pressure)
     float2* lmy = lds + line * LS;
@@ -99,85 +168,85 @@ __global__ __launch_bounds__(Plan<N>::RT, (Plan<N>::E <= 16 ? 4 : 2)) void row_p
     asm volatile("" : "+s"(tw0));
     float2 v[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = in.f2(voff, T * k * 8);
+    for (int k = 0; k < E; ++k) v[k] = in.f2(voff, T * k * 32);
     if (!active) {
 #pragma unroll
       for (int k = 0; k < E; ++k) v[k] = make_float2(0.f, 0.f);
     }
-    fft_line<N, false, 1, 0>(v, lb, 0, lmy, tw0);
-    const double2 rc = a.rowc2[active ? row : 0];
-    const float sy = a.conj ? -a.scale : a.scale;
-    chunked<E, 4>([&](int k) {
-      const int l = b + T * k;
-      const int nu = l < N / 2 ? l : l - N;
-      float2 p = cis_turns(phi2_turns(rc, (double)nu));
-      p = make_float2(p.x * a.scale, p.y * sy);
-      v[k] = cmul(v[k], p);
-    });
+    // first range-Doppler screen: Phi1 (M) or Phi3* (G)
+    {
+      const Quad q = conj ? phi3_quad(a.rowc3[rr], a, b, T) : phi1_quad(a.rowc1[rr], a, b, T);
+      apply_quad<E, false>(v, q, conj, 1.0f);
+    }
+    fft_line<N, false, 1, TW>(v, lb, 0, lmy, tw0);
+    apply_quad<E, true>(v, phi2_quad(a.rowc2[rr], b, T), conj, a.scale);
     const float2* tw = a.tw;
     asm volatile("" : "+s"(tw));
     asm volatile("" : "+v"(lb), "+v"(lmy));
-    fft_line<N, true, 1, 0>(v, lb, 0, lmy, tw);
+    fft_line<N, true, 1, TW>(v, lb, 0, lmy, tw);
+    // second range-Doppler screen: Phi3 (M) or Phi1* (G)
+    {
+      const Quad q = conj ? phi1_quad(a.rowc1[rr], a, b, T) : phi3_quad(a.rowc3[rr], a, b, T);
+      apply_quad<E, false>(v, q, conj, 1.0f);
+    }
     if (active) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) out.st(v[k], voff, T * k * 8);
+      for (int k = 0; k < E; ++k) out.st(v[k], voff, T * k * 32);
     }
   }
 }
 
 __device__ __forceinline__ int xcd_logical_block() {
   // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
-  // that consecutive logical ids (adjacent column tiles sharing cache lines)
-  // run on the same XCD and share its L2.
+  // that consecutive logical ids (adjacent column tiles) run on the same XCD.
   const int g = gridDim.x, w = blockIdx.x;
   if (g % 8 != 0) return w;
   return (w % 8) * (g / 8) + w / 8;
 }
 
-template <int N, int MODE, int PH>
+template <int N, int MODE>
 __global__ __launch_bounds__(Plan<N>::CT) void col_pass_kernel(ColArgs a) {
   using P = Plan<N>;
   constexpr int E = P::E, T = P::T, C = P::C, CT = P::CT;
+  constexpr int TW = 1;  // twiddle mode
   constexpr int LS = LdsSize<C, N>::value;
   __shared__ float2 lds[LS];
   __shared__ float red[CT / 64];
   const int c = threadIdx.x % C;
   const int b = threadIdx.x / C;
   const int ntiles = (a.nr + C - 1) / C;
-  const uint32_t nr = (uint32_t)a.nr;
-  const uint32_t bytes = clamp_bytes((size_t)N * a.nr * 8);
-  const Buf in0(a.in0, bytes), in1(a.in1, bytes), yb(a.y, bytes), out(a.out, bytes);
+  const uint32_t rmb = clamp_bytes((size_t)N * a.nr * 8), b4b = clamp_bytes(b4_bytes(N, a.nr));
+  const int in_layout = MODE == COL_FWD ? RM : B4;
+  const int out_layout = (MODE == COL_INV || (MODE == COL_A && (a.flags & 2))) ? RM : B4;
+  const Buf in0(a.in0, in_layout == RM ? rmb : b4b), in1(a.in1, b4b), yb(a.y, b4b);
+  const Buf out(a.out, out_layout == RM ? rmb : b4b), out2(a.out2, b4b);
   const Buf mask(a.mask, clamp_bytes(((size_t)N * a.nr + 31) / 32 * 4));
-  const Buf rowc(a.rowc, N * 16);
-  const uint32_t kbytes = T * nr * 8;       // byte stride between v[k] and v[k+1]
-  const uint32_t kmask = T * nr / 32 * 4;   // same, in the packed mask (nr % 32 == 0)
-  const uint32_t boff = (uint32_t)b * 16u;  // coefficient offset of row b
+  const uint32_t kmask = T * (uint32_t)a.nr / 32 * 4;  // mask byte step per k (T N_r % 32 == 0)
   float acc = 0.f;
   for (int tile = xcd_logical_block(); tile < ntiles; tile += gridDim.x) {
     const int j = tile * C + c;
     const bool active = j < a.nr;
     const int jj = active ? j : 0;
-    const uint32_t lane = (uint32_t)b * nr + jj;  // element index of v[0]
-    const uint32_t voff = lane * 8u;
-    const double2 cc = a.colc[jj];
-    // Opaque per-tile copy of the twiddle pointer: keeps the compiler from
-    // hoisting every pass's twiddles out of the tile loop (register pressure).
+    const Addr ai = col_addr(in_layout, b, jj, T, a.nr);
+    const Addr ab = col_addr(B4, b, jj, T, a.nr);
+    // blocked element index of (b, j): bit of the packed mask
+    const uint32_t e0 = (((uint32_t)(b >> 2) * (a.nr / 4) + (jj >> 2)) << 4) + ((b & 3) << 2) + (jj & 3);
+    const uint32_t moff = (e0 >> 5) * 4u, bit = e0 & 31u;
+    // Opaque per-tile copies: keep the compiler from hoisting every pass's
+    // twiddles and LDS addresses out of the tile loop (register pressure).
     const float2* tw = a.tw;
     asm volatile("" : "+s"(tw));
-    // Likewise for the lane's LDS coordinates: the exchange addresses are
-    // recomputed per tile instead of being held across the whole loop.
     int lb = b, lc = c;
     asm volatile("" : "+v"(lb), "+v"(lc));
     float2 v[E];
     if constexpr (MODE == COL_FWD) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) v[k] = in0.f2(voff, k * kbytes);
+      for (int k = 0; k < E; ++k) v[k] = in0.f2(ai.voff, k * ai.kstep);
       if (!active) {
 #pragma unroll
         for (int k = 0; k < E; ++k) v[k] = make_float2(0.f, 0.f);
       }
       if (a.flags & 1) {
-        const uint32_t moff = (lane >> 5) * 4u, bit = lane & 31u;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
           const uint32_t w = mask.u32(moff, k * kmask);
@@ -185,54 +254,37 @@ __global__ __launch_bounds__(Plan<N>::CT) void col_pass_kernel(ColArgs a) {
           acc = fmaf(v[k].x, v[k].x, fmaf(v[k].y, v[k].y, acc));
         }
       }
-      __builtin_amdgcn_sched_barrier(0);
-      fft_line<N, false, C, 1>(v, lb, lc, lds, tw);
-      chunked<E, 4>([&](int k) {
-        Turns u = col_turns<PH>(rowc, boff, T * k * 16, cc);
-        float2 p = cis_quadrant(u.r, u.q);
-        v[k] = a.conj ? cmulc(v[k], p) : cmul(v[k], p);
-      });
+      if ((a.flags & 4) && active) {
+#pragma unroll
+        for (int k = 0; k < E; ++k) out2.st(v[k], ab.voff, k * ab.kstep);
+      }
+      fft_line<N, false, C, TW>(v, lb, lc, lds, tw);
     } else if constexpr (MODE == COL_INV) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) v[k] = in0.f2(voff, k * kbytes);
+      for (int k = 0; k < E; ++k) v[k] = cscale(in0.f2(ai.voff, k * ai.kstep), a.scale);
       if (!active) {
 #pragma unroll
         for (int k = 0; k < E; ++k) v[k] = make_float2(0.f, 0.f);
       }
-      const float sy = a.conj ? -a.scale : a.scale;
-      chunked<E, 4>([&](int k) {
-        Turns u = col_turns<PH>(rowc, boff, T * k * 16, cc);
-        float2 p = cis_quadrant(u.r, u.q);
-        v[k] = cmul(v[k], make_float2(p.x * a.scale, p.y * sy));
-      });
-      fft_line<N, true, C, 1>(v, lb, lc, lds, tw);
+      fft_line<N, true, C, TW>(v, lb, lc, lds, tw);
     } else if constexpr (MODE == COL_A) {
-      // V = F^-1[Phi3 (Xt + mu W)] / N_a; X+ = S_sigma(V); Xt+ = Phi3* F X+
-      // (the screen is evaluated again on the way back: cheaper than keeping
-      // it in registers across two transforms)
+      // V = F^-1[Xt + mu Z] / N_a; X+ = S_sigma(V); Xt+ = F X+
       const bool first = a.flags & 1;
+      const float ms = a.mu * a.scale;
 #pragma unroll
-      for (int k = 0; k < E; ++k) v[k] = in1.f2(voff, k * kbytes);
+      for (int k = 0; k < E; ++k) v[k] = cscale(in1.f2(ab.voff, k * ab.kstep), ms);
       if (!first) {
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-          const float2 x = in0.f2(voff, k * kbytes);
-          v[k] = make_float2(fmaf(a.mu, v[k].x, x.x), fmaf(a.mu, v[k].y, x.y));
+          const float2 x = in0.f2(ab.voff, k * ab.kstep);
+          v[k] = make_float2(fmaf(a.scale, x.x, v[k].x), fmaf(a.scale, x.y, v[k].y));
         }
-      } else {
-#pragma unroll
-        for (int k = 0; k < E; ++k) v[k] = cscale(v[k], a.mu);
       }
       if (!active) {
 #pragma unroll
         for (int k = 0; k < E; ++k) v[k] = make_float2(0.f, 0.f);
       }
-      chunked<E, 4>([&](int k) {
-        Turns u = col_turns<3>(rowc, boff, T * k * 16, cc);
-        float2 p = cis_quadrant(u.r, u.q);
-        v[k] = cscale(cmul(v[k], p), a.scale);
-      });
-      fft_line<N, true, C, 1>(v, lb, lc, lds, tw);
+      fft_line<N, true, C, TW>(v, lb, lc, lds, tw);
       const float s2 = a.sigma * a.sigma;
 #pragma unroll
       for (int k = 0; k < E; ++k) {
@@ -242,47 +294,36 @@ __global__ __launch_bounds__(Plan<N>::CT) void col_pass_kernel(ColArgs a) {
       }
       if (!(a.flags & 2)) {
         asm volatile("" : "+s"(tw));
-        fft_line<N, false, C, 1>(v, lb, lc, lds, tw);
-        chunked<E, 4>([&](int k) {
-          Turns u = col_turns<3>(rowc, boff, T * k * 16, cc);
-          v[k] = cmulc(v[k], cis_quadrant(u.r, u.q));
-        });
+        asm volatile("" : "+v"(lb), "+v"(lc));
+        fft_line<N, false, C, TW>(v, lb, lc, lds, tw);
       }
     } else {  // COL_R
-      // GX = F^-1[Phi1* Wg] / N_a; R = m o (y - GX); out = Phi1 F R
+      // GX = F^-1[W] / N_a; R = m o y - m o GX; out = F R
 #pragma unroll
-      for (int k = 0; k < E; ++k) v[k] = in0.f2(voff, k * kbytes);
+      for (int k = 0; k < E; ++k) v[k] = cscale(in0.f2(ab.voff, k * ab.kstep), a.scale);
       if (!active) {
 #pragma unroll
         for (int k = 0; k < E; ++k) v[k] = make_float2(0.f, 0.f);
       }
-      chunked<E, 4>([&](int k) {
-        Turns u = col_turns<1>(rowc, boff, T * k * 16, cc);
-        float2 p = cis_quadrant(u.r, u.q);
-        v[k] = cscale(cmulc(v[k], p), a.scale);
-      });
-      fft_line<N, true, C, 1>(v, lb, lc, lds, tw);
-      const uint32_t moff = (lane >> 5) * 4u, bit = lane & 31u;
+      fft_line<N, true, C, TW>(v, lb, lc, lds, tw);
       const uint32_t act = active ? 1u : 0u;
       chunked<E, 4>([&](int k) {
         const uint32_t w = mask.u32(moff, k * kmask);
         const float keep = (float)((w >> bit) & act);
-        const float2 yy = yb.f2(voff, k * kbytes);
+        const float2 yy = yb.f2(ab.voff, k * ab.kstep);
         float2 r = cscale(csub(yy, v[k]), keep);
         acc = fmaf(r.x, r.x, fmaf(r.y, r.y, acc));
         asm volatile("" : "+v"(acc));  // accumulate here, not after the next transform
         v[k] = r;
       });
       asm volatile("" : "+s"(tw));
-      fft_line<N, false, C, 1>(v, lb, lc, lds, tw);
-      chunked<E, 4>([&](int k) {
-        Turns u = col_turns<1>(rowc, boff, T * k * 16, cc);
-        v[k] = cmul(v[k], cis_quadrant(u.r, u.q));
-      });
+      asm volatile("" : "+v"(lb), "+v"(lc));
+      fft_line<N, false, C, TW>(v, lb, lc, lds, tw);
     }
     if (active) {
+      const Addr ao = out_layout == RM ? col_addr(RM, b, jj, T, a.nr) : ab;
 #pragma unroll
-      for (int k = 0; k < E; ++k) out.st(v[k], voff, k * kbytes);
+      for (int k = 0; k < E; ++k) out.st(v[k], ao.voff, k * ao.kstep);
     }
   }
   const bool want_norm = (MODE == COL_R) || (MODE == COL_FWD && (a.flags & 1));
@@ -292,21 +333,16 @@ __global__ __launch_bounds__(Plan<N>::CT) void col_pass_kernel(ColArgs a) {
   }
 }
 
-// Host-side launch helpers (one set per length, instantiated in kern_<N>.hip).
-struct LaunchCfg {
-  int grid;
-  int block;
-};
-
+// Host-side launch helpers (one set per length, instantiated in kern_inst.hip).
 template <int N>
 struct Kernels {
   static hipError_t row(const RowArgs& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(row_pass_kernel<N>, dim3(grid), dim3(Plan<N>::RT), 0, s, a);
     return hipGetLastError();
   }
-  template <int MODE, int PH>
+  template <int MODE>
   static hipError_t col(const ColArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((col_pass_kernel<N, MODE, PH>), dim3(grid), dim3(Plan<N>::CT), 0, s, a);
+    hipLaunchKernelGGL((col_pass_kernel<N, MODE>), dim3(grid), dim3(Plan<N>::CT), 0, s, a);
     return hipGetLastError();
   }
 };

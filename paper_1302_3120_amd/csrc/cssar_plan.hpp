@@ -9,7 +9,11 @@ namespace cssar {
 
 template <int N> struct Plan;
 
-#define CSSAR_PLAN(NN, EE, CC, ...)                                                   \
+// Row passes: RT threads per workgroup handle LR rows (T = N / E threads
+// each).  With LR a multiple of 4, the lanes of a wave cover whole 128-byte
+// blocks of the blocked layout (see cssar_layout); LR = 1 is the fallback
+// for lines too long for four of them to share the LDS.
+#define CSSAR_PLAN(NN, EE, CC, RTT, ...)                                              \
   template <> struct Plan<NN> {                                                       \
     static constexpr int N = NN;                                                      \
     static constexpr int E = EE;                                                      \
@@ -20,23 +24,23 @@ template <int N> struct Plan;
     static constexpr int radix(int s) { return R[s]; }                                \
     static constexpr int sub(int s) { return s == 0 ? 1 : sub(s - 1) * R[s - 1]; }    \
     static constexpr int prod() { return sub(P); }                                    \
-    static constexpr int RT = T >= 256 ? T : 256; /* row-pass workgroup threads */    \
-    static constexpr int LR = RT / T;             /* rows per row-pass workgroup */   \
-    static constexpr int CT = C * T;              /* column-pass workgroup threads */ \
+    static constexpr int RT = RTT;    /* row-pass workgroup threads */                \
+    static constexpr int LR = RT / T; /* rows per row-pass workgroup */               \
+    static constexpr int CT = C * T;  /* column-pass workgroup threads */             \
   };
 
-//         N     E   C   radices
-CSSAR_PLAN(64, 16, 16, 16, 4)
-CSSAR_PLAN(128, 16, 16, 16, 8)
-CSSAR_PLAN(256, 16, 16, 16, 16)
-CSSAR_PLAN(512, 16, 16, 16, 16, 2)
-CSSAR_PLAN(768, 24, 16, 3, 8, 8, 4)
-CSSAR_PLAN(1024, 16, 16, 16, 16, 4)
-CSSAR_PLAN(1536, 24, 8, 3, 8, 8, 8)
-CSSAR_PLAN(2048, 16, 8, 16, 16, 8)
-CSSAR_PLAN(3072, 24, 4, 3, 8, 8, 8, 2)
-CSSAR_PLAN(4096, 16, 4, 16, 16, 16)
-CSSAR_PLAN(8192, 16, 2, 16, 16, 16, 2)
+//         N     E   C    RT   radices
+CSSAR_PLAN(64, 16, 16, 256, 16, 4)
+CSSAR_PLAN(128, 16, 16, 256, 16, 8)
+CSSAR_PLAN(256, 16, 16, 256, 16, 16)
+CSSAR_PLAN(512, 16, 16, 256, 16, 16, 2)
+CSSAR_PLAN(768, 24, 16, 256, 3, 8, 8, 4)
+CSSAR_PLAN(1024, 16, 16, 256, 16, 16, 4)
+CSSAR_PLAN(1536, 24, 8, 256, 3, 8, 8, 8)
+CSSAR_PLAN(2048, 16, 8, 512, 16, 16, 8)
+CSSAR_PLAN(3072, 24, 4, 512, 3, 8, 8, 8, 2)
+CSSAR_PLAN(4096, 16, 4, 1024, 16, 16, 16)
+CSSAR_PLAN(8192, 16, 2, 512, 16, 16, 16, 2)
 
 #undef CSSAR_PLAN
 
@@ -48,6 +52,8 @@ constexpr bool plan_ok() {
   for (int s = 0; s < P::P; ++s)
     if (P::E % P::R[s] != 0) return false;
   if (P::CT > 1024 || P::RT > 1024) return false;
+  if (P::RT % P::T != 0 || P::T % 4 != 0) return false;
+  if (!(P::LR == 1 || P::LR % 4 == 0)) return false;
   return true;
 }
 static_assert(plan_ok<64>() && plan_ok<128>() && plan_ok<256>() && plan_ok<512>(), "plan");

@@ -9,7 +9,7 @@ namespace cssar {
 struct RowArgs;
 struct ColArgs;
 
-enum ColKernel { CK_FWD1 = 0, CK_FWD3, CK_INV1, CK_INV3, CK_A, CK_R, CK_COUNT };
+enum ColKernel { CK_FWD = 0, CK_INV, CK_A, CK_R, CK_COUNT };
 
 struct KernelTable {
   int n, E, T, C, CT, RT, LR, passes;

@@ -21,19 +21,13 @@ const KernelTable* CSSAR_CAT(kernel_table_, CSSAR_N)() {
       {P::P > 0 ? P::R[0] : 0, P::P > 1 ? P::R[1] : 0, P::P > 2 ? P::R[2] : 0,
        P::P > 3 ? P::R[3] : 0, P::P > 4 ? P::R[4] : 0, 0, 0, 0},
       &K::row,
-      &K::template col<COL_FWD, 1>,
-      &K::template col<COL_FWD, 3>,
-      &K::template col<COL_INV, 1>,
-      &K::template col<COL_INV, 3>,
-      &K::template col<COL_A, 3>,
-      &K::template col<COL_R, 1>,
+      {&K::template col<COL_FWD>, &K::template col<COL_INV>, &K::template col<COL_A>,
+       &K::template col<COL_R>},
       reinterpret_cast<const void*>(&row_pass_kernel<CSSAR_N>),
-      {reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_FWD, 1>),
-       reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_FWD, 3>),
-       reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_INV, 1>),
-       reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_INV, 3>),
-       reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_A, 3>),
-       reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_R, 1>)},
+      {reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_FWD>),
+       reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_INV>),
+       reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_A>),
+       reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_R>)},
   };
   return &t;
 }

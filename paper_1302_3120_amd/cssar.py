@@ -26,8 +26,8 @@ SYMBOLS = (
     "cssar_plan_info", "cssar_profile_enable", "cssar_profile_read",
 )
 
-PROFILE_KINDS = ("row_M", "row_G", "col_fwd_phi1", "col_fwd_phi3c", "col_inv_phi1c",
-                 "col_inv_phi3", "col_update_threshold", "col_residual")
+PROFILE_KINDS = ("row_M", "row_G", "col_fwd", "col_inv", "col_update_threshold",
+                 "col_residual", "unused6", "unused7")
 
 
 class CssarError(RuntimeError):
@@ -154,18 +154,27 @@ class Operator:
             raise ValueError(f"{name} must be contiguous with shape {self.shape}")
         return t
 
-    def apply_G(self, x, out=None):
+    def _ws(self, ws, mode, device):
+        if ws is None:
+            return self.workspace(mode, device)
+        if ws.numel() * ws.element_size() < self.workspace_size(mode) or not ws.is_cuda:
+            raise ValueError("workspace too small")
+        return ws
+
+    def apply_G(self, x, out=None, ws=None):
         """y = G x."""
         x = self._arr(x, "x")
         out = torch.empty_like(x) if out is None else self._arr(out, "out")
-        _check(lib().cssar_apply_G(self._h, _ptr(x), _ptr(out), None, _stream()))
+        ws = self._ws(ws, 0, x.device)
+        _check(lib().cssar_apply_G(self._h, _ptr(x), _ptr(out), _ptr(ws), _stream()))
         return out
 
-    def apply_GH(self, y, out=None):
+    def apply_GH(self, y, out=None, ws=None):
         """x = G^H y = M y (the focusing chain)."""
         y = self._arr(y, "y")
         out = torch.empty_like(y) if out is None else self._arr(out, "out")
-        _check(lib().cssar_apply_GH(self._h, _ptr(y), _ptr(out), None, _stream()))
+        ws = self._ws(ws, 0, y.device)
+        _check(lib().cssar_apply_GH(self._h, _ptr(y), _ptr(out), _ptr(ws), _stream()))
         return out
 
     def pack_mask(self, mask):
@@ -180,6 +189,8 @@ class Operator:
         return bits
 
     def workspace(self, mode, device=None):
+        """A fresh workspace tensor for cssar_workspace_size(mode) bytes
+        (torch's allocator returns 256-byte aligned blocks)."""
         nbytes = self.workspace_size(mode)
         return torch.empty(max(nbytes, 8), dtype=torch.uint8, device=device or "cuda")
 
@@ -190,9 +201,7 @@ class Operator:
         if mask_bits.dtype != torch.int32 or not mask_bits.is_cuda:
             raise TypeError("mask_bits must come from pack_mask")
         out = torch.empty_like(y) if out is None else self._arr(out, "out")
-        ws = self.workspace(1, y.device) if ws is None else ws
-        if ws.numel() * ws.element_size() < self.workspace_size(1):
-            raise ValueError("workspace too small")
+        ws = self._ws(ws, 1, y.device)
         hist = torch.empty(int(iters), dtype=torch.float32, device=y.device) if resid else None
         _check(lib().cssar_ita_solve(self._h, _ptr(y), _ptr(mask_bits), float(lam),
                                      int(iters), _ptr(out),
