@@ -197,11 +197,22 @@ struct LdsSize {
 // (= v[q + (E/R) m]), applying w_{LR}^(j m) with j = beta mod L, and writing
 // y[(beta - j) R + j + L m].  After the last pass every output lands back in
 // its own thread's slot, so only the passes before it go through LDS.
-// TWM selects how the twiddles w^(j m), m < R, are obtained: 0 = one table
-// load each (exactly rounded values), 1 = one table load of w^j and products
-// of at most four factors for the rest (fewer loads and registers in flight).
-template <int N, int E, int R, int L, bool INV, int TWM>
-__device__ __forceinline__ void stockham_compute(float2 (&v)[E], int b, const float2* __restrict__ tw) {
+// Twiddle sources: w_N^e = exp(-2 pi i e / N) for 0 <= e < N.
+struct TwGlobal {  // FP32 table in global memory
+  const float2* p;
+  __device__ __forceinline__ float2 operator()(int e) const { return p[e]; }
+};
+struct TwLds {  // two-level table in LDS: w^e = lo[e % 64] hi[e / 64]
+  const float2* lo;
+  const float2* hi;
+  __device__ __forceinline__ float2 operator()(int e) const { return cmul(lo[e & 63], hi[e >> 6]); }
+};
+
+// Radix-R butterflies of one Stockham pass on the thread's registers.  The
+// twiddles w^(j m), m < R, come from one lookup of w^j and products of at
+// most four factors for the rest.
+template <int N, int E, int R, int L, bool INV, typename TW>
+__device__ __forceinline__ void stockham_compute(float2 (&v)[E], int b, const TW& tws) {
   constexpr int Q = E / R;
   constexpr int T = N / E;
 #pragma unroll
@@ -213,29 +224,23 @@ __device__ __forceinline__ void stockham_compute(float2 (&v)[E], int b, const fl
       const int beta = b + T * q;
       const int j = beta % L;
       constexpr int step = N / (L * R);
-      if constexpr (TWM == 0) {
-#pragma unroll
-      for (int m = 1; m < R; ++m) {
-        float2 w = tw[j * m * step];
-        a[m] = INV ? cmulc(a[m], w) : cmul(a[m], w);
-      }
-      } else {
-      // powers of w1 = w^j with multiplication depth <= 4
+      // w^m = w^hi * w^(m - hi) with hi the highest power of two <= m; each
+      // product is applied as soon as it exists
       float2 w[R];
-      w[1] = tw[j * step];
+      w[1] = tws(j * step);
       if (INV) w[1].y = -w[1].y;
+      a[1] = cmul(a[1], w[1]);
 #pragma unroll
       for (int m = 2; m < R; ++m) {
-        const int hi = 1 << (31 - __builtin_clz(m));  // highest power of two <= m
+        const int hi = 1 << (31 - __builtin_clz(m));
         w[m] = (m == hi) ? cmul(w[m / 2], w[m / 2]) : cmul(w[hi], w[m - hi]);
-      }
-#pragma unroll
-      for (int m = 1; m < R; ++m) a[m] = cmul(a[m], w[m]);
+        a[m] = cmul(a[m], w[m]);
       }
     }
     dft_reg<R, INV>(a);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[q + Q * m] = a[m];
+    if constexpr (Q > 1) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -286,19 +291,24 @@ __device__ __forceinline__ void stockham_exchange(float2 (&v)[E], int b, int c, 
   __syncthreads();
 }
 
-template <int N, bool INV, int C, int TWM, int S = 0>
-__device__ __forceinline__ void fft_line(float2 (&v)[Plan<N>::E], int b, int c, float2* lds,
-                                         const float2* __restrict__ tw) {
+template <int N, bool INV, int C, typename TW, int S = 0>
+__device__ __forceinline__ void fft_line(float2 (&v)[Plan<N>::E], int b, int c, float2* lds, const TW& tws) {
   using P = Plan<N>;
   if constexpr (S < P::P) {
     constexpr int R = P::radix(S);
     constexpr int L = P::sub(S);
     __builtin_amdgcn_sched_barrier(0);
-    stockham_compute<N, P::E, R, L, INV, TWM>(v, b, tw);
+    stockham_compute<N, P::E, R, L, INV>(v, b, tws);
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (S + 1 < P::P) stockham_exchange<N, P::E, R, L, C>(v, b, c, lds);
-    fft_line<N, INV, C, TWM, S + 1>(v, b, c, lds, tw);
+    fft_line<N, INV, C, TW, S + 1>(v, b, c, lds, tws);
   }
+}
+
+// Fill a two-level twiddle table (64 + N/64 entries) from the global table.
+template <int N>
+__device__ __forceinline__ void load_twiddle_table(float2* t, const float2* __restrict__ tw) {
+  for (int i = threadIdx.x; i < 64 + N / 64; i += blockDim.x) t[i] = tw[i < 64 ? i : 64 * (i - 64)];
 }
 
 // --------------------------------------------------------- phase screens --
@@ -324,13 +334,26 @@ __device__ __forceinline__ Quad quad_in_slot(double p0, double p1, double p2, in
   return q;
 }
 
+// 1: the hardware sine/cosine (argument in turns, |error| <= 1.3e-7 on
+// [-1/2, 1/2] measured on gfx950) after the FP64 reduction; 0: the Taylor
+// polynomial of cis_quadrant.
+#ifndef CSSAR_HWSIN
+#define CSSAR_HWSIN 1
+#endif
+
 // exp(2 pi i (A + B k + C k^2)) for a small integer k.
 __device__ __forceinline__ float2 cis_quad(const Quad& q, int k) {
   const double dk = (double)k;
+#if CSSAR_HWSIN
+  const double t = fma(fma(q.C, dk, q.B), dk, q.A);
+  const float r = (float)(t - rint(t));  // |r| <= 1/2 turn
+  return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
+#else
   const double t4 = 4.0 * fma(fma(q.C, dk, q.B), dk, q.A);  // quarter turns
   const double qn = rint(t4);
   const float r = (float)((t4 - qn) * 0.25);
   return cis_quadrant(r, (int)qn);
+#endif
 }
 
 // ------------------------------------------------------- buffer access --

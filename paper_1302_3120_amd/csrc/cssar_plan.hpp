@@ -10,9 +10,10 @@ namespace cssar {
 template <int N> struct Plan;
 
 // Row passes: RT threads per workgroup handle LR rows (T = N / E threads
-// each).  With LR a multiple of 4, the lanes of a wave cover whole 128-byte
-// blocks of the blocked layout (see cssar_layout); LR = 1 is the fallback
-// for lines too long for four of them to share the LDS.
+// each).  With LR a multiple of 4 the lanes of a wave cover whole 128-byte
+// blocks of the blocked layout; with LR = 2 two workgroups share each block
+// (64 bytes each), which halves the LDS per workgroup so that two fit on a
+// compute unit; LR = 1 is the fallback for the longest lines.
 #define CSSAR_PLAN(NN, EE, CC, RTT, ...)                                              \
   template <> struct Plan<NN> {                                                       \
     static constexpr int N = NN;                                                      \
@@ -29,18 +30,26 @@ template <int N> struct Plan;
     static constexpr int CT = C * T;  /* column-pass workgroup threads */             \
   };
 
+#ifndef CSSAR_E4096
+#define CSSAR_E4096 16
+#endif
+#ifndef CSSAR_LR4096
+#define CSSAR_LR4096 2
+#endif
+#define CSSAR_RT4096 (CSSAR_LR4096 * 4096 / CSSAR_E4096)
+
 //         N     E   C    RT   radices
 CSSAR_PLAN(64, 16, 16, 256, 16, 4)
 CSSAR_PLAN(128, 16, 16, 256, 16, 8)
 CSSAR_PLAN(256, 16, 16, 256, 16, 16)
 CSSAR_PLAN(512, 16, 16, 256, 16, 16, 2)
 CSSAR_PLAN(768, 24, 16, 256, 3, 8, 8, 4)
-CSSAR_PLAN(1024, 16, 16, 256, 16, 16, 4)
+CSSAR_PLAN(1024, 32, 16, 256, 16, 16, 4)
 CSSAR_PLAN(1536, 24, 8, 256, 3, 8, 8, 8)
-CSSAR_PLAN(2048, 16, 8, 512, 16, 16, 8)
+CSSAR_PLAN(2048, 32, 8, 256, 16, 16, 8)
 CSSAR_PLAN(3072, 24, 4, 512, 3, 8, 8, 8, 2)
-CSSAR_PLAN(4096, 16, 4, 1024, 16, 16, 16)
-CSSAR_PLAN(8192, 16, 2, 512, 16, 16, 16, 2)
+CSSAR_PLAN(4096, CSSAR_E4096, 4, CSSAR_RT4096, 16, 16, 16)
+CSSAR_PLAN(8192, 32, 2, 256, 16, 16, 16, 2)
 
 #undef CSSAR_PLAN
 
@@ -53,7 +62,7 @@ constexpr bool plan_ok() {
     if (P::E % P::R[s] != 0) return false;
   if (P::CT > 1024 || P::RT > 1024) return false;
   if (P::RT % P::T != 0 || P::T % 4 != 0) return false;
-  if (!(P::LR == 1 || P::LR % 4 == 0)) return false;
+  if (!(P::LR == 1 || P::LR == 2 || P::LR % 4 == 0)) return false;
   return true;
 }
 static_assert(plan_ok<64>() && plan_ok<128>() && plan_ok<256>() && plan_ok<512>(), "plan");
