@@ -9,8 +9,12 @@ and the FP64 oracle timed on the host cores.
 """
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -27,6 +31,16 @@ PASS_BYTES = {
     "col_update_threshold": 24.0, "col_residual": 24.125,
 }
 ITER_BYTES = 80.125  # per pixel per ITA iteration: row G, col R, row M, col A
+# Kernel symbol of each pass kind (row_M and row_G share one kernel).
+KIND_SYMBOL = {
+    "row_M": "row_pass_kernel<{n}>", "row_G": "row_pass_kernel<{n}>",
+    "col_fwd": "col_pass_kernel<{n}, 0>", "col_inv": "col_pass_kernel<{n}, 1>",
+    "col_update_threshold": "col_pass_kernel<{n}, 2>", "col_residual": "col_pass_kernel<{n}, 3>",
+}
+# Counter-based HBM bytes per dispatch, written by --rocprof-summary from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and a copy-kernel calibration.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ita_passes_sparse_4096.md")
+CAL_MIB = 256  # size of the calibration copy (read and written once each)
 
 
 def log(msg):
@@ -92,6 +106,122 @@ def cpu_baseline(shape, seed):
                        f"{shape[0]}x{shape[1]} scene, 50% mask; {dt:.1f} s")
 
 
+def kernel_source_digest():
+    """SHA-256 over the HIP kernel sources: counter figures taken from an
+    older version of the kernels are not reported."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1302_3120_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def copy_calibration(device, reps=3):
+    """A plain device-to-device copy of CAL_MIB MiB, for scaling the HBM byte
+    counters: it reads and writes exactly CAL_MIB MiB per dispatch."""
+    import torch
+    n = CAL_MIB * 2 ** 20 // 4
+    src = torch.ones(n, dtype=torch.float32, device=device)
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def _rows(pattern):
+    out = []
+    for f in sorted(glob.glob(pattern, recursive=True)):
+        with open(f, newline="") as fh:
+            out.extend(csv.DictReader(fh))
+    return out
+
+
+def rocprof_summary(stats_dir, fetch_dir, write_dir, n, command):
+    """Text summary of rocprofv3 output: per-kernel durations (kernel-trace
+    --stats) and per-dispatch HBM bytes (FETCH_SIZE and WRITE_SIZE runs, each
+    scaled so that the calibration copy reads and writes CAL_MIB MiB)."""
+    lines = ["# rocprofv3 summary: ITA passes at %dx%d complex64" % (n, n), "",
+             "Commands (from the repository root, on one MI355X):", ""]
+    lines += ["    " + c for c in command]
+    lines += ["", "## Kernel durations (--kernel-trace --stats)", "",
+              "| kernel | calls | average us | min us | max us | % of GPU time |",
+              "|---|---|---|---|---|---|"]
+    stats = sorted(_rows(os.path.join(stats_dir, "**", "*kernel_stats.csv")),
+                   key=lambda r: -float(r["Percentage"]))
+    for r in stats[:8]:
+        name = r["Name"] if len(r["Name"]) <= 90 else r["Name"][:87] + "..."
+        lines.append("| %s | %s | %.1f | %.1f | %.1f | %.2f |" % (
+            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    per = {}
+    for d, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        groups = {}
+        for r in _rows(os.path.join(d, "**", "*counter_collection.csv")):
+            if r["Counter_Name"] != counter:
+                continue
+            groups.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        copies = {k: v for k, v in groups.items() if "copy" in k.lower()}
+        if not copies:
+            raise SystemExit("no copy kernel in " + d)
+        # the calibration copy is the largest copy dispatch of the run
+        cal_name = max(copies, key=lambda k: max(copies[k]))
+        cal_kib = max(copies[cal_name])
+        factor = CAL_MIB * 1024.0 / cal_kib
+        per[counter] = (factor, cal_name, cal_kib,
+                        {k: (len(v), statistics.median(v)) for k, v in groups.items()})
+    lines += ["", "## HBM bytes per dispatch (--pmc FETCH_SIZE; --pmc WRITE_SIZE)", ""]
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        factor, cal_name, cal_kib, _ = per[counter]
+        short = cal_name if len(cal_name) <= 60 else cal_name[:57] + "..."
+        lines.append("- %s calibration: torch's device copy `%s` of %d MiB counts %.1f KiB per "
+                     "dispatch; scale factor %.4f" % (counter, short, CAL_MIB, cal_kib, factor))
+    lines += ["", "| kernel | dispatches | FETCH_SIZE KiB (median) | WRITE_SIZE KiB (median) "
+                  "| fetch MB (scaled) | write MB (scaled) |", "|---|---|---|---|---|---|"]
+    fetch_groups = per["FETCH_SIZE"][3]
+    write_groups = per["WRITE_SIZE"][3]
+    machine = []
+    for kind, sym in KIND_SYMBOL.items():
+        sym = sym.format(n=n)
+        fk = [k for k in fetch_groups if sym in k]
+        wk = [k for k in write_groups if sym in k]
+        if not fk or not wk:
+            continue
+        cnt, f_kib = fetch_groups[fk[0]]
+        _, w_kib = write_groups[wk[0]]
+        fb = f_kib * 1024 * per["FETCH_SIZE"][0]
+        wb = w_kib * 1024 * per["WRITE_SIZE"][0]
+        if kind != "row_G":
+            lines.append("| %s | %d | %.1f | %.1f | %.1f | %.1f |" % (
+                fk[0], cnt, f_kib, w_kib, fb / 1e6, wb / 1e6))
+        machine.append("traffic %s %.0f %.0f" % (kind, fb, wb))
+    lines += ["", "Algorithmic bytes per dispatch: 16 B/pixel (row passes), 24 B/pixel (update and "
+                  "residual column passes; + 1/8 B/pixel mask for the residual pass).", "",
+              "Machine-readable lines (kind, fetch bytes, write bytes per dispatch, scaled):", ""]
+    lines += ["    " + m for m in machine]
+    lines += ["    kernel_sources_sha256 " + kernel_source_digest(), ""]
+    return "\n".join(lines)
+
+
+def load_traffic():
+    """Per-kind scaled HBM bytes per dispatch from the committed summary, or
+    None when it is missing or the kernel sources changed since."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    out, digest = {}, None
+    for line in text.splitlines():
+        w = line.split()
+        if len(w) == 4 and w[0] == "traffic":
+            out[w[1]] = float(w[2]) + float(w[3])
+        elif len(w) == 2 and w[0] == "kernel_sources_sha256":
+            digest = w[1]
+    if digest != kernel_source_digest():
+        return None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,7 +232,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the event-instrumented region (plain timing only)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help=f"also run a {CAL_MIB} MiB device copy (for counter calibration)")
+    ap.add_argument("--rocprof-summary", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="print a text summary of rocprofv3 output and exit (no GPU)")
+    ap.add_argument("--command", action="append", default=[],
+                    help="command line recorded in the --rocprof-summary text")
     args = ap.parse_args()
+
+    if args.rocprof_summary:
+        print(rocprof_summary(*args.rocprof_summary, args.size, args.command))
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the single-scene "
@@ -159,13 +299,30 @@ def main():
             gbytes = PASS_BYTES[kind] * n / 1e9
             kernels[kind] = {"launches": cnt, "avg_us": avg_us, "algo_GB": gbytes,
                              "GBs": gbytes / (avg_us * 1e-6), "total_ms": ms}
-        dom = max(kernels, key=lambda kk: kernels[kk]["total_ms"])
-        kd = kernels[dom]
-        rec["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": kd["GBs"],
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": kd["GBs"] / HBM_PEAK_GBS, "traffic": None}
+        # The dominant kernel is the symbol with the most GPU time: the row
+        # passes of M and G are one kernel and are counted together.
+        by_sym = {}
+        for kind, kd in kernels.items():
+            sym = KIND_SYMBOL[kind].format(n=shape[1] if kind.startswith("row") else shape[0])
+            agg = by_sym.setdefault(sym, {"kinds": [], "ms": 0.0, "cnt": 0, "algo_GB": kd["algo_GB"]})
+            agg["kinds"].append(kind)
+            agg["ms"] += kd["total_ms"]
+            agg["cnt"] += kd["launches"]
+        dom = max(by_sym, key=lambda k: by_sym[k]["ms"])
+        agg = by_sym[dom]
+        avg_us = 1e3 * agg["ms"] / agg["cnt"]
+        gbs = agg["algo_GB"] / (avg_us * 1e-6)
+        traffic = load_traffic() if shape == (4096, 4096) else None
+        rec["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": gbs / HBM_PEAK_GBS,
+                           "traffic": traffic.get(agg["kinds"][0]) if traffic else None,
+                           "kernel": dom, "pass_kinds": agg["kinds"], "avg_us": avg_us,
+                           "launches": agg["cnt"], "algorithmic_bytes": agg["algo_GB"] * 1e9}
         rec["kernels"] = kernels
         rec["profiled_region_iterations_per_s"] = args.steps * args.iters / dt2
+
+    if args.copy_calibration:
+        copy_calibration(dev)
 
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host (one iteration)")
