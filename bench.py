@@ -76,6 +76,87 @@ def make_problem(op, shape, seed, density, rate, snr_db, device):
     return y, bits, lam, k
 
 
+def make_batched_problem(ops, wl, device):
+    """The 64-scene workload on the GPU (torch's seeded generator): per scene
+    a sparse scene of 50-300 point targets, y = m o (G x + s n) with the
+    library's G at 20 dB, mask rate U(0.3, 0.7), lambda by the sparsity rule."""
+    import numpy as np
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(wl["seed"])
+    r = np.random.default_rng(wl["seed"])
+    ys, bits, lams = [], [], []
+    for op in ops:
+        na, nr = op.shape
+        k = int(r.integers(wl["targets"][0], wl["targets"][1] + 1))
+        rate = float(r.uniform(*wl["mask_rate"]))
+        x = torch.zeros(na * nr, dtype=torch.complex64, device=device)
+        idx = torch.randperm(na * nr, generator=g, device=device)[:k]
+        amp = 0.5 + 0.5 * torch.rand(k, generator=g, device=device)
+        ph = 2 * np.pi * torch.rand(k, generator=g, device=device)
+        x[idx] = torch.polar(amp, ph)
+        clean = op.apply_G(x.view(na, nr))
+        m = torch.rand(na, nr, generator=g, device=device) < rate
+        p_sig = float((clean.abs() ** 2)[m].mean())
+        sn = (p_sig / 10.0 ** (wl["snr_db"] / 10.0)) ** 0.5
+        n = torch.randn(na, nr, dtype=torch.complex64, generator=g, device=device)
+        y = torch.where(m, clean + sn * n, torch.zeros_like(clean))
+        lams.append(float(torch.topk(op.apply_GH(y).abs().flatten(), k + 1).values[-1]))
+        ys.append(y)
+        bits.append(op.pack_mask(m))
+    return ys, bits, lams
+
+
+def bench_batched(steps, iters, device):
+    """Batched solver on the 64-scene workload against the plain loop of
+    per-scene solves, same GPU, same inputs."""
+    import torch
+    import inputs
+    import paper_1302_3120_amd as pk
+    wl = inputs.workload("batched_64")
+    shapes = inputs.batched_shapes(wl["count"], wl["seed"], wl["sizes"])
+    ops = [pk.make_operator(inputs.RADAR_STRIPMAP, sh) for sh in shapes]
+    log(f"bench: batched workload, {len(shapes)} scenes")
+    ys, bits, lams = make_batched_problem(ops, wl, device)
+    px = sum(a * b for a, b in shapes)
+    outs = [torch.empty_like(y) for y in ys]
+    wss = [op.workspace(1, device) for op in ops]
+
+    def plain():
+        for s, op in enumerate(ops):
+            op.ita_solve(ys[s], bits[s], lams[s], iters, out=outs[s], ws=wss[s])
+
+    t_plain = time_steps(plain, steps, 1)
+    del wss
+    b = pk.make_batch(ops)
+    ws = b.workspace(device)
+    t0 = time.perf_counter()
+    b.autotune(ws)
+    t_tune = time.perf_counter() - t0
+    bouts = [torch.empty_like(y) for y in ys]
+
+    def batched():
+        b.ita_solve(ys, bits, lams, iters, outs=bouts, ws=ws)
+
+    t_batch = time_steps(batched, steps, 1)
+    worst = 0.0
+    for o, r in zip(bouts, outs):
+        worst = max(worst, float((o - r).abs().pow(2).sum().sqrt() / r.abs().pow(2).sum().sqrt()))
+    its_b = steps * iters / t_batch
+    its_p = steps * iters / t_plain
+    return {
+        "workload": f"batched_64: {len(shapes)} scenes, dims from {list(wl['sizes'])}, "
+                    f"{px / 1e6:.1f} Mpx, {iters} iterations per step",
+        "iterations_per_s": its_b, "plain_loop_iterations_per_s": its_p,
+        "speedup_vs_plain_loop": its_b / its_p,
+        "Mpx_iterations_per_s": its_b * px / 1e6,
+        "algorithmic_GBs": its_b * px * ITER_BYTES / 1e9,
+        "hbm_frac_algorithmic": its_b * px * ITER_BYTES / (HBM_PEAK_GBS * 1e9),
+        "rel_l2_vs_plain_loop": worst, "autotune_s": t_tune,
+        "choices": b.describe().strip().splitlines(),
+    }
+
+
 def time_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -233,6 +314,8 @@ def main():
     ap.add_argument("--iters", type=int, default=100, help="ITA iterations per step")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-scene batched-versus-plain-loop measurement")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the event-instrumented region (plain timing only)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -326,6 +409,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(dev)
+
+    if not args.no_batched:
+        rec["batched"] = bench_batched(3, args.iters, dev)
 
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host (one iteration)")

@@ -120,6 +120,61 @@ int cssar_pack_mask(const cssar_op* op, const void* mask_bytes, void* mask_bits,
 int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda,
                     int iters, void* x_out, float* resid_hist, void* ws, void* stream);
 
+/* ---------------------------------------------------------------- batch --
+ * Many independent scenes (any supported shapes) solved together.  The
+ * paper's method is single-scene; batching is an execution strategy: each
+ * ITA step of eq. (th2d) / Algorithm 1 is applied to every scene by grouped
+ * persistent kernels, one launch per pass kind and line length (a table of
+ * per-scene arguments maps a global work index to (scene, line group)), so
+ * an iteration over 64 scenes of four sizes takes 16 launches instead of 256.
+ * The middle iterations can be replayed from a captured HIP graph, and an
+ * autotuner picks, per line length and pass kind, the kernel plan variant
+ * and the number of resident workgroups per compute unit by measuring them.
+ * Results equal those of cssar_ita_solve on each scene (bit for bit with
+ * the default plans, within rounding with tuned plans); residual norms and
+ * the non-finite check are not formed. */
+typedef struct cssar_batch cssar_batch;
+
+/* Group count >= 1 operators (all made on the current device).  The
+ * operators must outlive the batch.  Allocates the batch's small device
+ * argument tables and a pinned host staging buffer. */
+int cssar_make_batch(cssar_op* const* ops, int count, cssar_batch** out);
+
+/* Release a batch (NULL is accepted; the operators are not released). */
+int cssar_destroy_batch(cssar_batch* b);
+
+/* Workspace bytes of cssar_ita_solve_batched: three blocked arrays per scene
+ * (cssar_workspace_size(op, 1) each, 256-byte aligned).  0 for NULL. */
+size_t cssar_batch_workspace_size(const cssar_batch* b);
+
+/* Launch mode of the middle iterations: 0 direct launches, 1 replay of a HIP
+ * graph of one iteration (captured on first use on a private stream,
+ * launched on the caller's stream).  The autotuner also sets it. */
+int cssar_batch_set_graph(cssar_batch* b, int on);
+
+/* Measure the plan variants and workgroups-per-CU choices of the row pass
+ * and of the residual and update column passes for every line length of the
+ * batch, and graph versus direct launches; keep the fastest.  ws: a batch
+ * workspace (cssar_batch_workspace_size bytes; clobbered).  cache_path:
+ * NULL, or a text file of earlier results (one line per choice, keyed by the
+ * device, pass, length and amount of work); matching lines are used without
+ * measuring and new results are appended.  Synchronises the stream. */
+int cssar_batch_autotune(cssar_batch* b, void* ws, const char* cache_path, void* stream);
+
+/* Current choices as text (one line per pass kind and length, then the
+ * launch mode) into buf (NUL-terminated, truncated to len).  Returns the
+ * full length. */
+int cssar_batch_describe(const cssar_batch* b, char* buf, int len);
+
+/* Iterative thresholding on every scene s (the iteration of cssar_ita_solve):
+ * ys[s], mask_bits[s] (cssar_pack_mask with that scene's operator),
+ * lambdas[s] >= 0 and x_outs[s] as for cssar_ita_solve; host arrays of
+ * count device pointers / floats; ws: cssar_batch_workspace_size bytes.
+ * Calls sharing one batch must be ordered on one stream. */
+int cssar_ita_solve_batched(cssar_batch* b, const void* const* ys, const void* const* mask_bits,
+                            const float* lambdas, int iters, void* const* x_outs, void* ws,
+                            void* stream);
+
 /* Synchronise the stream and report a deferred device-side error of this
  * operator (CSSAR_ENONFINITE if a residual norm was NaN/Inf), clearing it. */
 int cssar_sync_status(cssar_op* op, void* stream);

@@ -1,9 +1,9 @@
 """Build libcssar.so for gfx950 with hipcc (in-tree).
 
-The pass kernels of every supported line length are compiled from one
-source (csrc/kern_inst.hip) with a different CSSAR_N, in parallel, then
-linked with the C-ABI object (csrc/cssar_api.hip) into
-paper_1302_3120_amd/libcssar.so.
+The pass kernels of every compiled plan (supported line length and plan
+variant) are compiled from one source (csrc/kern_inst.hip) with different
+CSSAR_N / CSSAR_V, in parallel, then linked with the C-ABI objects
+(csrc/cssar_api.hip, csrc/cssar_batch.hip) into paper_1302_3120_amd/libcssar.so.
 """
 
 import concurrent.futures as cf
@@ -17,6 +17,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcssar.so")
 LENGTHS = (64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096, 8192)
+# (length, variant) pairs: every length has variant 0; these also have 1
+VARIANT1 = (512, 1024, 1536, 2048, 4096)
+PLANS = tuple((n, 0) for n in LENGTHS) + tuple((n, 1) for n in VARIANT1)
 ARCH = "gfx950"
 
 
@@ -50,12 +53,13 @@ def build(jobs=None, verbose=False, report=False):
     flags = common_flags()
     extra = ["-Rpass-analysis=kernel-resource-usage"] if report else []
     cmds = []
-    for n in LENGTHS:
-        obj = os.path.join(BUILD, f"kern_{n}.o")
-        cmds.append([cc, *flags, *extra, f"-DCSSAR_N={n}", "-c",
+    for n, v in PLANS:
+        obj = os.path.join(BUILD, f"kern_{n}_{v}.o")
+        cmds.append([cc, *flags, *extra, f"-DCSSAR_N={n}", f"-DCSSAR_V={v}", "-c",
                      os.path.join(CSRC, "kern_inst.hip"), "-o", obj])
-    api_obj = os.path.join(BUILD, "cssar_api.o")
-    cmds.append([cc, *flags, "-c", os.path.join(CSRC, "cssar_api.hip"), "-o", api_obj])
+    for src in ("cssar_api.hip", "cssar_batch.hip"):
+        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        cmds.append([cc, *flags, "-c", os.path.join(CSRC, src), "-o", obj])
     jobs = jobs or min(len(cmds), max(1, os.cpu_count() or 1))
     outs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

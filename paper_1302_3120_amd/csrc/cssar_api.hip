@@ -1,26 +1,19 @@
 // C ABI of the library: operator construction (FP64 coefficient vectors,
 // twiddle tables, launch plan), operator application G / G^H and the
 // iterative thresholding solver.  See include/cssar.h for the contract.
-#include <hip/hip_runtime.h>
-
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <string>
-#include <vector>
 
-#include "../../include/cssar.h"
-#include "cssar_kernels.hpp"
-#include "cssar_table.hpp"
+#include "cssar_internal.hpp"
 
 using namespace cssar;
+using namespace cssar::detail;
 
-namespace {
-
-constexpr double kC = 299792458.0;
-constexpr int kMaxPartials = 8192;
+namespace cssar {
+namespace detail {
 
 thread_local std::string g_last_error;
 
@@ -34,59 +27,19 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                               \
-  do {                                                                              \
-    hipError_t e_ = (expr);                                                         \
-    if (e_ != hipSuccess)                                                           \
-      return fail(CSSAR_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),       \
-                  __FILE__, __LINE__);                                              \
-  } while (0)
-
-const KernelTable* table_for(int n) {
-  switch (n) {
-#define CSSAR_CASE(NN) \
-  case NN:             \
-    return kernel_table_##NN();
-    CSSAR_FOR_EACH_LENGTH(CSSAR_CASE)
+// Kernel table of a (length, plan variant) pair, or NULL if not compiled.
+const KernelTable* table_for(int n, int v) {
+#define CSSAR_CASE(NN, VV) \
+  if (n == NN && v == VV) return kernel_table_##NN##_##VV();
+  CSSAR_FOR_EACH_PLAN(CSSAR_CASE)
 #undef CSSAR_CASE
-    default:
-      return nullptr;
-  }
+  return nullptr;
 }
 
 int signed_bin(int k, int n) { return k < (n + 1) / 2 ? k : k - n; }
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-}  // namespace
-
-struct cssar_op {
-  int na = 0, nr = 0;
-  cssar_params p{};
-  int device = 0;
-  int cus = 0;
-  const KernelTable* ka = nullptr;  // azimuth length N_a (column passes)
-  const KernelTable* kr = nullptr;  // range length N_r (row passes)
-  double2* rowc1 = nullptr;         // per Doppler bin: Phi1 (a1, d1)
-  double2* rowc2 = nullptr;         //                  Phi2 (a2, b2)
-  double2* rowc3 = nullptr;         //                  Phi3 (D, b3)
-  float2* tw_a = nullptr;           // w_{N_a}^k
-  float2* tw_r = nullptr;           // w_{N_r}^k
-  float* partials = nullptr;        // per-block partial sums
-  unsigned* counter = nullptr;      // [0] last-block counter, [1] status bits
-  int grid_row = 0;
-  int grid_col[CK_COUNT] = {};
-  // optional per-launch HIP event timing (cssar_profile_enable)
-  bool profiling = false;
-  struct Rec {
-    int kind;
-    hipEvent_t start, stop;
-  };
-  std::vector<Rec> recs;
-  std::vector<hipEvent_t> pool;
-};
-
-namespace {
 
 // FP64 coefficient vectors of the three phase screens (turns = radians/2pi).
 //   D(f) = sqrt(1 - (lambda f / (2 v))^2), D_ref = 1 (zero Doppler centroid)
@@ -223,7 +176,8 @@ int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
   return timed(op, 2 + which, s, [&] { return op->ka->col[which](a, op->grid_col[which], s); });
 }
 
-}  // namespace
+}  // namespace detail
+}  // namespace cssar
 
 extern "C" {
 

@@ -291,9 +291,11 @@ __device__ __forceinline__ void stockham_exchange(float2 (&v)[E], int b, int c, 
   __syncthreads();
 }
 
-template <int N, bool INV, int C, typename TW, int S = 0>
-__device__ __forceinline__ void fft_line(float2 (&v)[Plan<N>::E], int b, int c, float2* lds, const TW& tws) {
-  using P = Plan<N>;
+// One length-N transform (plan P) of the line held by the thread's
+// registers (x[b + T k] in v[k]), lines interleaved C-wide in LDS.
+template <class P, bool INV, int C, typename TW, int S = 0>
+__device__ __forceinline__ void fft_line(float2 (&v)[P::E], int b, int c, float2* lds, const TW& tws) {
+  constexpr int N = P::N;
   if constexpr (S < P::P) {
     constexpr int R = P::radix(S);
     constexpr int L = P::sub(S);
@@ -301,7 +303,7 @@ __device__ __forceinline__ void fft_line(float2 (&v)[Plan<N>::E], int b, int c, 
     stockham_compute<N, P::E, R, L, INV>(v, b, tws);
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (S + 1 < P::P) stockham_exchange<N, P::E, R, L, C>(v, b, c, lds);
-    fft_line<N, INV, C, TW, S + 1>(v, b, c, lds, tws);
+    fft_line<P, INV, C, TW, S + 1>(v, b, c, lds, tws);
   }
 }
 

@@ -1,0 +1,74 @@
+// Declarations shared by the C-ABI sources (operator state, argument
+// builders, launch helpers).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cssar.h"
+#include "cssar_kernels.hpp"
+#include "cssar_table.hpp"
+
+namespace cssar {
+namespace detail {
+
+constexpr double kC = 299792458.0;
+constexpr int kMaxPartials = 8192;
+
+// Records a thread-local message (cssar_last_error) and returns code.
+int fail(int code, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return ::cssar::detail::fail(CSSAR_EHIP, "%s: %s (%s:%d)", #expr,                \
+                                   hipGetErrorString(e_), __FILE__, __LINE__);         \
+  } while (0)
+
+const KernelTable* table_for(int n, int v = 0);
+size_t align256(size_t n);
+int occupancy(const void* fn, int block);
+int grid_for(int work, int cus, int per_cu);
+
+}  // namespace detail
+}  // namespace cssar
+
+// Operator state: parameters, plans and the O(N_a + N_r) device tables.
+struct cssar_op {
+  int na = 0, nr = 0;
+  cssar_params p{};
+  int device = 0;
+  int cus = 0;
+  const cssar::KernelTable* ka = nullptr;  // azimuth length N_a (column passes)
+  const cssar::KernelTable* kr = nullptr;  // range length N_r (row passes)
+  double2* rowc1 = nullptr;         // per Doppler bin: Phi1 (a1, d1)
+  double2* rowc2 = nullptr;         //                  Phi2 (a2, b2)
+  double2* rowc3 = nullptr;         //                  Phi3 (D, b3)
+  float2* tw_a = nullptr;           // w_{N_a}^k
+  float2* tw_r = nullptr;           // w_{N_r}^k
+  float* partials = nullptr;        // per-block partial sums
+  unsigned* counter = nullptr;      // [0] last-block counter, [1] status bits
+  int grid_row = 0;
+  int grid_col[cssar::CK_COUNT] = {};
+  // optional per-launch HIP event timing (cssar_profile_enable)
+  bool profiling = false;
+  struct Rec {
+    int kind;
+    hipEvent_t start, stop;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace cssar {
+namespace detail {
+
+ColArgs col_args(const cssar_op* op);
+RowArgs row_args(const cssar_op* op, const void* in, void* out, int conj);
+int check_op(const cssar_op* op);
+
+}  // namespace detail
+}  // namespace cssar

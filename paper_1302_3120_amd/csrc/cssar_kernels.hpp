@@ -14,11 +14,12 @@
 // quadratic polynomial in the element's offset along the line.
 //
 // Every kernel is persistent: a workgroup walks over units (row groups or
-// column tiles) with a stride of the grid size, and the loads of its next
-// unit are issued into a second register set before the current unit is
-// transformed, so HBM traffic overlaps the FFT work.  Nothing inside the
-// transform reads global memory (twiddles come from a small LDS table), so
-// waiting for the current unit never waits for the prefetch.
+// column tiles) with a stride of the grid size; several workgroups share a
+// compute unit so that one's loads overlap another's FFT work.  Nothing
+// inside the transform reads global memory (twiddles come from a small LDS
+// table).  The grouped variants walk over the units of many arrays of one
+// line length (the batched solver): a table of per-array arguments and the
+// prefix sums of their unit counts map a global unit index to (array, unit).
 //
 // Memory layouts.  Arrays handed over by the caller are row-major ("RM":
 // element (i, j) at byte 8 (i N_r + j)).  Arrays that stay inside a solve or
@@ -35,12 +36,6 @@
 namespace cssar {
 
 enum Layout { RM = 0, B4 = 1 };
-
-#ifndef CSSAR_PREFETCH
-#define CSSAR_PREFETCH 0
-#endif
-// 1: the next unit's loads are issued before the current unit is transformed
-constexpr bool kPrefetch = CSSAR_PREFETCH != 0;
 
 __host__ __device__ constexpr uint32_t b4_stride(int nr) { return 32u * (uint32_t)nr + 128u; }
 __host__ __device__ constexpr size_t b4_bytes(int na, int nr) { return (size_t)(na / 4) * b4_stride(nr); }
@@ -148,212 +143,240 @@ __device__ __forceinline__ void apply_quad(float2 (&v)[E], const Quad& q, bool c
 
 __device__ __forceinline__ int xcd_logical_block() {
   // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
-  // that consecutive logical ids (adjacent column tiles) run on the same XCD.
+  // that consecutive logical ids (adjacent units) run on the same XCD.
   const int g = gridDim.x, w = blockIdx.x;
   if (g % 8 != 0) return w;
   return (w % 8) * (g / 8) + w / 8;
 }
 
+// Units of many arrays in one launch: array s owns global units
+// start[s] .. start[s+1]-1; args points at count RowArgs or ColArgs.
+struct GroupArgs {
+  const void* args;
+  const int* start;  // count + 1 prefix sums
+  int count;
+  int total;         // start[count]
+};
+
+// Largest s with start[s] <= u (u is uniform across the workgroup, so the
+// search runs on scalar loads).
+__device__ __forceinline__ int group_find(const int* __restrict__ start, int count, int u) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= u) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------- row pass --
 // Row pass (B4 in and out).  Thread t of a workgroup with LR = 4 G rows:
 // g = t / 4T picks the block row, and within it lane bits 0-1 give j % 4,
 // bits 2-3 the row in the block, the rest the block along the row, so the
-// 64 lanes of a wave read 4 consecutive 128-byte blocks.
-template <int N>
-__global__ __launch_bounds__(Plan<N>::RT) void row_pass_kernel(RowArgs a) {
-  using P = Plan<N>;
-  constexpr int E = P::E, T = P::T, LR = P::LR;
-  // the rows handled together share one LDS buffer, interleaved element by
-  // element like the columns of a column tile (conflict-free exchanges)
-  constexpr int LI = LR >= 4 ? 4 : LR;
-  constexpr int LS = LdsSize<LI, N>::value;
-  __shared__ float2 lds[(LR / LI) * LS];
-  __shared__ float2 twl[64 + N / 64];
-  load_twiddle_table<N>(twl, a.tw);
-  __syncthreads();
-  // lane bits 0-1: j % 4; then log2(LI) bits: the row inside the block (or
-  // half block); the rest: the block along the row
+// 64 lanes of a wave read 4 consecutive 128-byte blocks.  With LR = 2, lane
+// bit 2 picks the row and a wave reads the halves of 8 blocks.
+template <class P>
+struct RowLane {
   int line, b;
-  if constexpr (LR == 1) {
-    line = 0;
-    b = threadIdx.x;
-  } else if constexpr (LR == 2) {
-    line = (threadIdx.x >> 2) & 1;
-    b = (threadIdx.x & 3) | ((threadIdx.x >> 3) << 2);
-  } else {
-    const int g = threadIdx.x / (4 * T), t = threadIdx.x % (4 * T);
-    line = 4 * g + ((t >> 2) & 3);
-    b = (t & 3) | ((t >> 4) << 2);
+  __device__ __forceinline__ RowLane() {
+    constexpr int T = P::T, LR = P::LR;
+    if constexpr (LR == 1) {
+      line = 0;
+      b = threadIdx.x;
+    } else if constexpr (LR == 2) {
+      line = (threadIdx.x >> 2) & 1;
+      b = (threadIdx.x & 3) | ((threadIdx.x >> 3) << 2);
+    } else {
+      const int g = threadIdx.x / (4 * T), t = threadIdx.x % (4 * T);
+      line = 4 * g + ((t >> 2) & 3);
+      b = (t & 3) | ((t >> 4) << 2);
+    }
   }
-  const int lsub = line % LI;  // position inside the interleaved buffer
+};
+
+// The rows handled together share one LDS buffer, interleaved element by
+// element like the columns of a column tile (conflict-free exchanges).
+template <class P>
+struct RowLds {
+  static constexpr int LI = P::LR >= 4 ? 4 : P::LR;
+  static constexpr int LS = LdsSize<LI, P::N>::value;
+  static constexpr int size = (P::LR / LI) * LS;
+};
+
+// One unit (LR rows) of the row pass of array a:
+//   M: x Phi1 -> F_tau -> x Phi2 / N_r -> F_tau^-1 -> x Phi3
+//   G: x Phi3* -> F_tau -> x Phi2* / N_r -> F_tau^-1 -> x Phi1*
+template <class P>
+__device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane<P>& ln, float2* lds,
+                                         const float2* twl) {
+  constexpr int N = P::N, E = P::E, T = P::T, LR = P::LR;
+  constexpr int LI = RowLds<P>::LI, LS = RowLds<P>::LS;
   const uint32_t S = b4_stride(N);
   const uint32_t bytes = clamp_bytes(b4_bytes(a.na, N));
   const Buf in(a.in, bytes), out(a.out, bytes);
   const bool conj = a.conj != 0;
-  const int groups = a.na / LR;  // N_a is a multiple of LR
-  auto voff_of = [&](int row) {
-    return (uint32_t)(row >> 2) * S + (uint32_t)(b >> 2) * 128u + (uint32_t)(row & 3) * 32u + (uint32_t)(b & 3) * 8u;
-  };
-  // prefetch registers: the next unit's data and its three coefficient pairs
-  float2 vn[E];
-  double2 c1n, c2n, c3n;
-  auto fetch = [&](int gi) {
-    const int row = gi * LR + line;
-    const uint32_t vo = voff_of(row);
+  const int b = ln.b, line = ln.line;
+  const int row = gi * LR + line;
+  const uint32_t vo = (uint32_t)(row >> 2) * S + (uint32_t)(b >> 2) * 128u + (uint32_t)(row & 3) * 32u +
+                      (uint32_t)(b & 3) * 8u;
+  float2 v[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) vn[k] = in.f2(vo, T * k * 32);
-    c1n = a.rowc1[row];
-    c2n = a.rowc2[row];
-    c3n = a.rowc3[row];
-  };
-  int gi = LR == 2 ? xcd_logical_block() : (int)blockIdx.x;
-  if (kPrefetch && gi < groups) fetch(gi);
-  for (; gi < groups; gi += gridDim.x) {
-    const int row = gi * LR + line;
-    if (!kPrefetch) fetch(gi);
-    float2 v[E];
+  for (int k = 0; k < E; ++k) v[k] = in.f2(vo, T * k * 32);
+  const double2 c1 = a.rowc1[row], c2 = a.rowc2[row], c3 = a.rowc3[row];
+  int lb = b, lc = line % LI;
+  asm volatile("" : "+v"(lb), "+v"(lc));  // recompute LDS addresses per unit (register pressure)
+  float2* lmy = lds + (line / LI) * LS;
+  asm volatile("" : "+v"(lmy));
+  const TwLds tws{twl, twl + 64};
+  // first range-Doppler screen: Phi1 (M) or Phi3* (G)
+  apply_quad<E, false>(v, conj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), conj, 1.0f);
+  fft_line<P, false, LI>(v, lb, lc, lmy, tws);
+  apply_quad<E, true>(v, phi2_quad(c2, b, T), conj, a.scale);
+  asm volatile("" : "+v"(lb), "+v"(lc), "+v"(lmy));
+  fft_line<P, true, LI>(v, lb, lc, lmy, tws);
+  // second range-Doppler screen: Phi3 (M) or Phi1* (G)
+  apply_quad<E, false>(v, conj ? phi1_quad(c1, a, b, T) : phi3_quad(c3, a, b, T), conj, 1.0f);
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = vn[k];
-    const double2 c1 = c1n, c2 = c2n, c3 = c3n;
-    if (kPrefetch && gi + (int)gridDim.x < groups) fetch(gi + gridDim.x);
-    int lb = b, lc = lsub;
-    asm volatile("" : "+v"(lb), "+v"(lc));  // recompute LDS addresses per unit (register pressure)
-    float2* lmy = lds + (line / LI) * LS;
-    asm volatile("" : "+v"(lmy));
-    const TwLds tws{twl, twl + 64};
-    // first range-Doppler screen: Phi1 (M) or Phi3* (G)
-    apply_quad<E, false>(v, conj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), conj, 1.0f);
-    fft_line<N, false, LI>(v, lb, lc, lmy, tws);
-    apply_quad<E, true>(v, phi2_quad(c2, b, T), conj, a.scale);
-    asm volatile("" : "+v"(lb), "+v"(lc), "+v"(lmy));
-    fft_line<N, true, LI>(v, lb, lc, lmy, tws);
-    // second range-Doppler screen: Phi3 (M) or Phi1* (G)
-    apply_quad<E, false>(v, conj ? phi1_quad(c1, a, b, T) : phi3_quad(c3, a, b, T), conj, 1.0f);
-    const uint32_t vo = voff_of(row);
-#pragma unroll
-    for (int k = 0; k < E; ++k) out.st(v[k], vo, T * k * 32);
+  for (int k = 0; k < E; ++k) out.st(v[k], vo, T * k * 32);
+}
+
+template <class P>
+__global__ __launch_bounds__(P::RT) void row_pass_kernel(RowArgs a) {
+  __shared__ float2 lds[RowLds<P>::size];
+  __shared__ float2 twl[64 + P::N / 64];
+  load_twiddle_table<P::N>(twl, a.tw);
+  __syncthreads();
+  const RowLane<P> ln;
+  const int units = a.na / P::LR;  // N_a is a multiple of LR
+  for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x)
+    row_unit<P>(a, gi, ln, lds, twl);
+}
+
+template <class P>
+__global__ __launch_bounds__(P::RT) void row_group_kernel(GroupArgs g) {
+  __shared__ float2 lds[RowLds<P>::size];
+  __shared__ float2 twl[64 + P::N / 64];
+  const RowArgs* __restrict__ args = (const RowArgs*)g.args;
+  load_twiddle_table<P::N>(twl, args[0].tw);  // w_N depends on N only
+  __syncthreads();
+  const RowLane<P> ln;
+  for (int u = xcd_logical_block(); u < g.total; u += gridDim.x) {
+    const int s = group_find(g.start, g.count, u);
+    row_unit<P>(args[s], u - g.start[s], ln, lds, twl);
   }
 }
 
-template <int N, int MODE>
-__global__ __launch_bounds__(Plan<N>::CT) void col_pass_kernel(ColArgs a) {
-  using P = Plan<N>;
-  constexpr int E = P::E, T = P::T, C = P::C, CT = P::CT;
-  constexpr int LS = LdsSize<C, N>::value;
-  __shared__ float2 lds[LS];
-  __shared__ float2 twl[64 + N / 64];
-  __shared__ float red[CT / 64];
-  load_twiddle_table<N>(twl, a.tw);
-  __syncthreads();
-  const int c = threadIdx.x % C;
-  const int b = threadIdx.x / C;
-  const int ntiles = a.nr / C;  // N_r is a multiple of C
+// ---------------------------------------------------------- column pass --
+// One tile (C adjacent columns) of a column pass of array a.  Returns the
+// thread's share of the tile's squared norm (FWD with the mask, R).
+template <class P, int MODE>
+__device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int c, float2* lds,
+                                          const float2* twl) {
+  constexpr int N = P::N, E = P::E, T = P::T, C = P::C;
   const uint32_t rmb = clamp_bytes((size_t)N * a.nr * 8), b4b = clamp_bytes(b4_bytes(N, a.nr));
   constexpr int in_layout = MODE == COL_FWD ? RM : B4;
   const int out_layout = (MODE == COL_INV || (MODE == COL_A && (a.flags & 2))) ? RM : B4;
   const Buf in0(a.in0, in_layout == RM ? rmb : b4b), in1(a.in1, b4b), yb(a.y, b4b);
   const Buf out(a.out, out_layout == RM ? rmb : b4b), out2(a.out2, b4b);
-  const Buf mask(a.mask, clamp_bytes(((size_t)N * a.nr + 31) / 32 * 4));
-  const uint32_t kmask = T * (uint32_t)a.nr / 32 * 4;  // mask byte step per k (T N_r % 32 == 0)
   const bool first = (MODE == COL_A) && (a.flags & 1);
-  // prefetch registers of the next tile: x (main input) and, for the update
-  // pass, z (second input Z)
-  float2 xn[E], zn[E];
-  auto fetch = [&](int tile) {
-    const int j = tile * C + c;
-    const Addr ai = col_addr(in_layout, b, j, T, a.nr);
-    if constexpr (MODE == COL_A) {
-#pragma unroll
-      for (int k = 0; k < E; ++k) zn[k] = in1.f2(ai.voff, k * ai.kstep);
-      if (!first) {
-#pragma unroll
-        for (int k = 0; k < E; ++k) xn[k] = in0.f2(ai.voff, k * ai.kstep);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < E; ++k) xn[k] = in0.f2(ai.voff, k * ai.kstep);
-    }
-  };
+  const int j = tile * C + c;
+  const Addr ai = col_addr(in_layout, b, j, T, a.nr);
+  const Addr ab = col_addr(B4, b, j, T, a.nr);
   float acc = 0.f;
-  int tile = xcd_logical_block();
-  if (kPrefetch && tile < ntiles) fetch(tile);
-  for (; tile < ntiles; tile += gridDim.x) {
-    const int j = tile * C + c;
-    if (!kPrefetch) fetch(tile);
-    const Addr ab = col_addr(B4, b, j, T, a.nr);
-    float2 v[E], y2[E];
-    if constexpr (MODE == COL_A) {
-      // V = F^-1[Xt + mu Z] / N_a
-      const float ms = a.mu * a.scale;
+  float2 v[E], y2[E];
+  if constexpr (MODE == COL_A) {
+    // V = F^-1[Xt + mu Z] / N_a
+    const float ms = a.mu * a.scale;
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = cscale(in1.f2(ai.voff, k * ai.kstep), ms);
+    if (!first) {
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        v[k] = cscale(zn[k], ms);
-        if (!first) v[k] = make_float2(fmaf(a.scale, xn[k].x, v[k].x), fmaf(a.scale, xn[k].y, v[k].y));
-      }
-    } else if constexpr (MODE == COL_FWD) {
-#pragma unroll
-      for (int k = 0; k < E; ++k) v[k] = xn[k];
-    } else {
-#pragma unroll
-      for (int k = 0; k < E; ++k) v[k] = cscale(xn[k], a.scale);
-      if constexpr (MODE == COL_R) {
-        // m o y of this tile (issued before any prefetch of the next tile)
-#pragma unroll
-        for (int k = 0; k < E; ++k) y2[k] = yb.f2(ab.voff, k * ab.kstep);
+        const float2 x = in0.f2(ai.voff, k * ai.kstep);
+        v[k] = make_float2(fmaf(a.scale, x.x, v[k].x), fmaf(a.scale, x.y, v[k].y));
       }
     }
-    const int next = tile + gridDim.x;
-    if (kPrefetch && next < ntiles) fetch(next);
-    const TwLds tws{twl, twl + 64};
-    int lb = b, lc = c;
-    asm volatile("" : "+v"(lb), "+v"(lc));  // recompute LDS addresses per tile
-    if constexpr (MODE == COL_FWD) {
-      if (a.flags & 1) {
-        // blocked element index of (b, j) addresses the packed mask
-        const uint32_t e0 = (((uint32_t)(b >> 2) * (a.nr / 4) + (j >> 2)) << 4) + ((b & 3) << 2) + (j & 3);
-        const uint32_t moff = (e0 >> 5) * 4u, bit = e0 & 31u;
+  } else if constexpr (MODE == COL_FWD) {
 #pragma unroll
-        for (int k = 0; k < E; ++k) {
-          const uint32_t w = mask.u32(moff, k * kmask);
-          const bool keep = (w >> bit) & 1u;
-          if (!keep) v[k] = make_float2(0.f, 0.f);
-          acc = fmaf(v[k].x, v[k].x, fmaf(v[k].y, v[k].y, acc));
-          if (a.flags & 4)
-            out2.st(keep ? v[k] : make_float2(__uint_as_float(kUnsampled), 0.f), ab.voff, k * ab.kstep);
-        }
-      }
-      fft_line<N, false, C>(v, lb, lc, lds, tws);
-    } else if constexpr (MODE == COL_INV) {
-      fft_line<N, true, C>(v, lb, lc, lds, tws);
-    } else if constexpr (MODE == COL_A) {
-      fft_line<N, true, C>(v, lb, lc, lds, tws);
-      // X+ = S_sigma(V)
-      const float s2 = a.sigma * a.sigma;
+    for (int k = 0; k < E; ++k) v[k] = in0.f2(ai.voff, k * ai.kstep);
+  } else {
 #pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const float m2 = fmaf(v[k].x, v[k].x, v[k].y * v[k].y);
-        const float f = m2 > s2 ? fmaf(-a.sigma, rsqrtf(m2), 1.0f) : 0.0f;
-        v[k] = cscale(v[k], f);
-      }
-      if (!(a.flags & 2)) {
-        asm volatile("" : "+v"(lb), "+v"(lc));
-        fft_line<N, false, C>(v, lb, lc, lds, tws);  // Xt+ = F X+
-      }
-    } else {  // COL_R: GX = F^-1[W] / N_a; R = m o y - m o GX; out = F R
-      fft_line<N, true, C>(v, lb, lc, lds, tws);
+    for (int k = 0; k < E; ++k) v[k] = cscale(in0.f2(ai.voff, k * ai.kstep), a.scale);
+    if constexpr (MODE == COL_R) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const bool keep = __float_as_uint(y2[k].x) != kUnsampled;
-        const float2 r = keep ? csub(y2[k], v[k]) : make_float2(0.f, 0.f);
-        acc = fmaf(r.x, r.x, fmaf(r.y, r.y, acc));
-        v[k] = r;
-      }
-      asm volatile("" : "+v"(lb), "+v"(lc));
-      fft_line<N, false, C>(v, lb, lc, lds, tws);
+      for (int k = 0; k < E; ++k) y2[k] = yb.f2(ab.voff, k * ab.kstep);
     }
-    const Addr ao = out_layout == RM ? col_addr(RM, b, j, T, a.nr) : ab;
-#pragma unroll
-    for (int k = 0; k < E; ++k) out.st(v[k], ao.voff, k * ao.kstep);
   }
+  const TwLds tws{twl, twl + 64};
+  int lb = b, lc = c;
+  asm volatile("" : "+v"(lb), "+v"(lc));  // recompute LDS addresses per tile
+  if constexpr (MODE == COL_FWD) {
+    if (a.flags & 1) {
+      const Buf mask(a.mask, clamp_bytes(((size_t)N * a.nr + 31) / 32 * 4));
+      const uint32_t kmask = T * (uint32_t)a.nr / 32 * 4;  // mask byte step per k (T N_r % 32 == 0)
+      // blocked element index of (b, j) addresses the packed mask
+      const uint32_t e0 = (((uint32_t)(b >> 2) * (a.nr / 4) + (j >> 2)) << 4) + ((b & 3) << 2) + (j & 3);
+      const uint32_t moff = (e0 >> 5) * 4u, bit = e0 & 31u;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const uint32_t w = mask.u32(moff, k * kmask);
+        const bool keep = (w >> bit) & 1u;
+        if (!keep) v[k] = make_float2(0.f, 0.f);
+        acc = fmaf(v[k].x, v[k].x, fmaf(v[k].y, v[k].y, acc));
+        if (a.flags & 4)
+          out2.st(keep ? v[k] : make_float2(__uint_as_float(kUnsampled), 0.f), ab.voff, k * ab.kstep);
+      }
+    }
+    fft_line<P, false, C>(v, lb, lc, lds, tws);
+  } else if constexpr (MODE == COL_INV) {
+    fft_line<P, true, C>(v, lb, lc, lds, tws);
+  } else if constexpr (MODE == COL_A) {
+    fft_line<P, true, C>(v, lb, lc, lds, tws);
+    // X+ = S_sigma(V)
+    const float s2 = a.sigma * a.sigma;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const float m2 = fmaf(v[k].x, v[k].x, v[k].y * v[k].y);
+      const float f = m2 > s2 ? fmaf(-a.sigma, rsqrtf(m2), 1.0f) : 0.0f;
+      v[k] = cscale(v[k], f);
+    }
+    if (!(a.flags & 2)) {
+      asm volatile("" : "+v"(lb), "+v"(lc));
+      fft_line<P, false, C>(v, lb, lc, lds, tws);  // Xt+ = F X+
+    }
+  } else {  // COL_R: GX = F^-1[W] / N_a; R = m o y - m o GX; out = F R
+    fft_line<P, true, C>(v, lb, lc, lds, tws);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const bool keep = __float_as_uint(y2[k].x) != kUnsampled;
+      const float2 r = keep ? csub(y2[k], v[k]) : make_float2(0.f, 0.f);
+      acc = fmaf(r.x, r.x, fmaf(r.y, r.y, acc));
+      v[k] = r;
+    }
+    asm volatile("" : "+v"(lb), "+v"(lc));
+    fft_line<P, false, C>(v, lb, lc, lds, tws);
+  }
+  const Addr ao = out_layout == RM ? col_addr(RM, b, j, T, a.nr) : ab;
+#pragma unroll
+  for (int k = 0; k < E; ++k) out.st(v[k], ao.voff, k * ao.kstep);
+  return acc;
+}
+
+template <class P, int MODE>
+__global__ __launch_bounds__(P::CT) void col_pass_kernel(ColArgs a) {
+  constexpr int C = P::C, CT = P::CT;
+  __shared__ float2 lds[LdsSize<C, P::N>::value];
+  __shared__ float2 twl[64 + P::N / 64];
+  __shared__ float red[CT / 64];
+  load_twiddle_table<P::N>(twl, a.tw);
+  __syncthreads();
+  const int c = threadIdx.x % C;
+  const int b = threadIdx.x / C;
+  const int ntiles = a.nr / C;  // N_r is a multiple of C
+  float acc = 0.f;
+  for (int tile = xcd_logical_block(); tile < ntiles; tile += gridDim.x)
+    acc += col_unit<P, MODE>(a, tile, b, c, lds, twl);
   const bool want_norm = (MODE == COL_R) || (MODE == COL_FWD && (a.flags & 1));
   if (want_norm) {
     const float part = block_sum<CT>(acc, red);
@@ -361,16 +384,42 @@ __global__ __launch_bounds__(Plan<N>::CT) void col_pass_kernel(ColArgs a) {
   }
 }
 
-// Host-side launch helpers (one set per length, instantiated in kern_inst.hip).
-template <int N>
+// Grouped column pass (batched solver): no norms are formed.
+template <class P, int MODE>
+__global__ __launch_bounds__(P::CT) void col_group_kernel(GroupArgs g) {
+  constexpr int C = P::C;
+  __shared__ float2 lds[LdsSize<C, P::N>::value];
+  __shared__ float2 twl[64 + P::N / 64];
+  const ColArgs* __restrict__ args = (const ColArgs*)g.args;
+  load_twiddle_table<P::N>(twl, args[0].tw);
+  __syncthreads();
+  const int c = threadIdx.x % C;
+  const int b = threadIdx.x / C;
+  for (int u = xcd_logical_block(); u < g.total; u += gridDim.x) {
+    const int s = group_find(g.start, g.count, u);
+    (void)col_unit<P, MODE>(args[s], u - g.start[s], b, c, lds, twl);
+  }
+}
+
+// Host-side launch helpers (one set per plan, instantiated in kern_inst.hip).
+template <class P>
 struct Kernels {
   static hipError_t row(const RowArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(row_pass_kernel<N>, dim3(grid), dim3(Plan<N>::RT), 0, s, a);
+    hipLaunchKernelGGL(row_pass_kernel<P>, dim3(grid), dim3(P::RT), 0, s, a);
     return hipGetLastError();
   }
   template <int MODE>
   static hipError_t col(const ColArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((col_pass_kernel<N, MODE>), dim3(grid), dim3(Plan<N>::CT), 0, s, a);
+    hipLaunchKernelGGL((col_pass_kernel<P, MODE>), dim3(grid), dim3(P::CT), 0, s, a);
+    return hipGetLastError();
+  }
+  static hipError_t row_group(const GroupArgs& g, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(row_group_kernel<P>, dim3(grid), dim3(P::RT), 0, s, g);
+    return hipGetLastError();
+  }
+  template <int MODE>
+  static hipError_t col_group(const GroupArgs& g, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((col_group_kernel<P, MODE>), dim3(grid), dim3(P::CT), 0, s, g);
     return hipGetLastError();
   }
 };

@@ -1,22 +1,26 @@
-// Compile-time FFT plans: for each supported line length N, the number of
-// elements each thread holds (E, so T = N / E threads per line) and the radix
-// sequence of the Stockham passes (every radix divides E).  Column passes
-// process tiles of C adjacent columns (C lines interleaved in LDS); row
-// passes process LR rows per workgroup.
+// Compile-time FFT plans: for each supported line length N and plan variant
+// V, the number of elements each thread holds (E, so T = N / E threads per
+// line) and the radix sequence of the Stockham passes (every radix divides
+// E).  Column passes process tiles of C adjacent columns (C lines interleaved
+// in LDS); row passes process LR rows per workgroup.  Variant 0 is the
+// default of every length; variant 1, where it exists, is an alternative
+// schedule (other E, radices, tile width or rows per workgroup) that the
+// batched solver's autotuner may pick after measuring both.
 #pragma once
 
 namespace cssar {
 
-template <int N> struct Plan;
+template <int N, int V> struct Plan;
 
 // Row passes: RT threads per workgroup handle LR rows (T = N / E threads
 // each).  With LR a multiple of 4 the lanes of a wave cover whole 128-byte
 // blocks of the blocked layout; with LR = 2 two workgroups share each block
 // (64 bytes each), which halves the LDS per workgroup so that two fit on a
 // compute unit; LR = 1 is the fallback for the longest lines.
-#define CSSAR_PLAN(NN, EE, CC, RTT, ...)                                              \
-  template <> struct Plan<NN> {                                                       \
+#define CSSAR_PLAN(NN, VV, EE, CC, RTT, ...)                                          \
+  template <> struct Plan<NN, VV> {                                                   \
     static constexpr int N = NN;                                                      \
+    static constexpr int V = VV;                                                      \
     static constexpr int E = EE;                                                      \
     static constexpr int T = NN / EE;                                                 \
     static constexpr int C = CC; /* column tile width */                              \
@@ -38,26 +42,30 @@ template <int N> struct Plan;
 #endif
 #define CSSAR_RT4096 (CSSAR_LR4096 * 4096 / CSSAR_E4096)
 
-//         N     E   C    RT   radices
-CSSAR_PLAN(64, 16, 16, 256, 16, 4)
-CSSAR_PLAN(128, 16, 16, 256, 16, 8)
-CSSAR_PLAN(256, 16, 16, 256, 16, 16)
-CSSAR_PLAN(512, 16, 16, 256, 16, 16, 2)
-CSSAR_PLAN(768, 24, 16, 256, 3, 8, 8, 4)
-CSSAR_PLAN(1024, 32, 16, 256, 16, 16, 4)
-CSSAR_PLAN(1536, 24, 8, 256, 3, 8, 8, 8)
-CSSAR_PLAN(2048, 32, 8, 256, 16, 16, 8)
-CSSAR_PLAN(3072, 24, 4, 512, 3, 8, 8, 8, 2)
-CSSAR_PLAN(4096, CSSAR_E4096, 4, CSSAR_RT4096, 16, 16, 16)
-CSSAR_PLAN(8192, 32, 2, 256, 16, 16, 16, 2)
+//         N    V   E   C    RT   radices
+CSSAR_PLAN(64, 0, 16, 16, 256, 16, 4)
+CSSAR_PLAN(128, 0, 16, 16, 256, 16, 8)
+CSSAR_PLAN(256, 0, 16, 16, 256, 16, 16)
+CSSAR_PLAN(512, 0, 8, 16, 256, 8, 8, 8)
+CSSAR_PLAN(512, 1, 16, 16, 256, 16, 16, 2)
+CSSAR_PLAN(768, 0, 24, 16, 256, 3, 8, 8, 4)
+CSSAR_PLAN(1024, 0, 16, 8, 256, 16, 16, 4)
+CSSAR_PLAN(1024, 1, 32, 16, 256, 16, 16, 4)
+CSSAR_PLAN(1536, 0, 24, 4, 128, 3, 8, 8, 8)
+CSSAR_PLAN(1536, 1, 24, 8, 256, 3, 8, 8, 8)
+CSSAR_PLAN(2048, 0, 16, 8, 256, 16, 16, 8)
+CSSAR_PLAN(2048, 1, 32, 8, 256, 16, 16, 8)
+CSSAR_PLAN(3072, 0, 24, 4, 512, 3, 8, 8, 8, 2)
+CSSAR_PLAN(4096, 0, CSSAR_E4096, 4, CSSAR_RT4096, 16, 16, 16)
+CSSAR_PLAN(4096, 1, 32, 4, 256, 16, 16, 16)
+CSSAR_PLAN(8192, 0, 32, 2, 256, 16, 16, 16, 2)
 
 #undef CSSAR_PLAN
 
 // Sanity checks evaluated at compile time for every plan.
-template <int N>
+template <class P>
 constexpr bool plan_ok() {
-  using P = Plan<N>;
-  if (P::prod() != N) return false;
+  if (P::prod() != P::N) return false;
   for (int s = 0; s < P::P; ++s)
     if (P::E % P::R[s] != 0) return false;
   if (P::CT > 1024 || P::RT > 1024) return false;
@@ -65,11 +73,19 @@ constexpr bool plan_ok() {
   if (!(P::LR == 1 || P::LR == 2 || P::LR % 4 == 0)) return false;
   return true;
 }
-static_assert(plan_ok<64>() && plan_ok<128>() && plan_ok<256>() && plan_ok<512>(), "plan");
-static_assert(plan_ok<768>() && plan_ok<1024>() && plan_ok<1536>() && plan_ok<2048>(), "plan");
-static_assert(plan_ok<3072>() && plan_ok<4096>() && plan_ok<8192>(), "plan");
+
+// Every (length, variant) pair that is compiled.
+#define CSSAR_FOR_EACH_PLAN(X)                                                    \
+  X(64, 0) X(128, 0) X(256, 0) X(512, 0) X(512, 1) X(768, 0) X(1024, 0) X(1024, 1) \
+  X(1536, 0) X(1536, 1) X(2048, 0) X(2048, 1) X(3072, 0) X(4096, 0) X(4096, 1) X(8192, 0)
+
+#define CSSAR_CHECK_PLAN(NN, VV) static_assert(plan_ok<Plan<NN, VV>>(), "plan");
+CSSAR_FOR_EACH_PLAN(CSSAR_CHECK_PLAN)
+#undef CSSAR_CHECK_PLAN
 
 #define CSSAR_FOR_EACH_LENGTH(X) \
   X(64) X(128) X(256) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096) X(8192)
+
+constexpr int kMaxVariants = 2;
 
 }  // namespace cssar

@@ -1,37 +1,34 @@
-// Per-length table of pass launchers and plan constants, filled by
-// kern_inst.hip for every supported length.
+// Per-plan table of pass launchers and plan constants, filled by
+// kern_inst.hip for every compiled (length, variant) pair.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "cssar_plan.hpp"
 
 namespace cssar {
 
 struct RowArgs;
 struct ColArgs;
+struct GroupArgs;
 
 enum ColKernel { CK_FWD = 0, CK_INV, CK_A, CK_R, CK_COUNT };
 
 struct KernelTable {
-  int n, E, T, C, CT, RT, LR, passes;
+  int n, variant, E, T, C, CT, RT, LR, passes;
   int radices[8];
   hipError_t (*row)(const RowArgs&, int, hipStream_t);
   hipError_t (*col[CK_COUNT])(const ColArgs&, int, hipStream_t);
+  hipError_t (*row_group)(const GroupArgs&, int, hipStream_t);
+  hipError_t (*col_group[CK_COUNT])(const GroupArgs&, int, hipStream_t);
   const void* row_fn;
   const void* col_fn[CK_COUNT];
+  const void* row_group_fn;
+  const void* col_group_fn[CK_COUNT];
 };
 
-#define CSSAR_DECL_TABLE(NN) const KernelTable* kernel_table_##NN();
-CSSAR_DECL_TABLE(64)
-CSSAR_DECL_TABLE(128)
-CSSAR_DECL_TABLE(256)
-CSSAR_DECL_TABLE(512)
-CSSAR_DECL_TABLE(768)
-CSSAR_DECL_TABLE(1024)
-CSSAR_DECL_TABLE(1536)
-CSSAR_DECL_TABLE(2048)
-CSSAR_DECL_TABLE(3072)
-CSSAR_DECL_TABLE(4096)
-CSSAR_DECL_TABLE(8192)
+#define CSSAR_DECL_TABLE(NN, VV) const KernelTable* kernel_table_##NN##_##VV();
+CSSAR_FOR_EACH_PLAN(CSSAR_DECL_TABLE)
 #undef CSSAR_DECL_TABLE
 
 }  // namespace cssar

@@ -1,33 +1,41 @@
-// Instantiates the pass kernels of one line length (CSSAR_N, set by the build)
-// and exposes them through a KernelTable.  Compiled once per length so the
-// heavily unrolled kernels build in parallel.
+// Instantiates the pass kernels of one plan (length CSSAR_N, variant
+// CSSAR_V, set by the build) and exposes them through a KernelTable.
+// Compiled once per plan so the heavily unrolled kernels build in parallel.
 #include "cssar_kernels.hpp"
 #include "cssar_table.hpp"
 
-#ifndef CSSAR_N
-#error "CSSAR_N must be defined"
+#if !defined(CSSAR_N) || !defined(CSSAR_V)
+#error "CSSAR_N and CSSAR_V must be defined"
 #endif
 
 namespace cssar {
 
-#define CSSAR_CAT2(a, b) a##b
-#define CSSAR_CAT(a, b) CSSAR_CAT2(a, b)
+#define CSSAR_CAT4(a, b, c, d) a##b##c##d
+#define CSSAR_TABLE_NAME(n, v) CSSAR_CAT4(kernel_table_, n, _, v)
 
-const KernelTable* CSSAR_CAT(kernel_table_, CSSAR_N)() {
-  using K = Kernels<CSSAR_N>;
-  using P = Plan<CSSAR_N>;
+const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
+  using P = Plan<CSSAR_N, CSSAR_V>;
+  using K = Kernels<P>;
   static const KernelTable t = {
-      CSSAR_N, P::E, P::T, P::C, P::CT, P::RT, P::LR, P::P,
+      CSSAR_N, CSSAR_V, P::E, P::T, P::C, P::CT, P::RT, P::LR, P::P,
       {P::P > 0 ? P::R[0] : 0, P::P > 1 ? P::R[1] : 0, P::P > 2 ? P::R[2] : 0,
        P::P > 3 ? P::R[3] : 0, P::P > 4 ? P::R[4] : 0, 0, 0, 0},
       &K::row,
       {&K::template col<COL_FWD>, &K::template col<COL_INV>, &K::template col<COL_A>,
        &K::template col<COL_R>},
-      reinterpret_cast<const void*>(&row_pass_kernel<CSSAR_N>),
-      {reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_FWD>),
-       reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_INV>),
-       reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_A>),
-       reinterpret_cast<const void*>(&col_pass_kernel<CSSAR_N, COL_R>)},
+      &K::row_group,
+      {&K::template col_group<COL_FWD>, &K::template col_group<COL_INV>,
+       &K::template col_group<COL_A>, &K::template col_group<COL_R>},
+      reinterpret_cast<const void*>(&row_pass_kernel<P>),
+      {reinterpret_cast<const void*>(&col_pass_kernel<P, COL_FWD>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_INV>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_A>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_R>)},
+      reinterpret_cast<const void*>(&row_group_kernel<P>),
+      {reinterpret_cast<const void*>(&col_group_kernel<P, COL_FWD>),
+       reinterpret_cast<const void*>(&col_group_kernel<P, COL_INV>),
+       reinterpret_cast<const void*>(&col_group_kernel<P, COL_A>),
+       reinterpret_cast<const void*>(&col_group_kernel<P, COL_R>)},
   };
   return &t;
 }

@@ -24,6 +24,9 @@ SYMBOLS = (
     "cssar_apply_G", "cssar_apply_GH", "cssar_pack_mask", "cssar_ita_solve",
     "cssar_sync_status", "cssar_last_error", "cssar_supported_length",
     "cssar_plan_info", "cssar_profile_enable", "cssar_profile_read",
+    "cssar_make_batch", "cssar_destroy_batch", "cssar_batch_workspace_size",
+    "cssar_batch_set_graph", "cssar_batch_autotune", "cssar_batch_describe",
+    "cssar_ita_solve_batched",
 )
 
 PROFILE_KINDS = ("row_M", "row_G", "col_fwd", "col_inv", "col_update_threshold",
@@ -79,10 +82,21 @@ def lib():
         L.cssar_profile_enable.argtypes = [vp, i]
         L.cssar_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double * 8),
                                          ctypes.POINTER(ctypes.c_long * 8)]
+        pp = ctypes.POINTER(vp)
+        L.cssar_make_batch.argtypes = [pp, i, pp]
+        L.cssar_destroy_batch.argtypes = [vp]
+        L.cssar_batch_workspace_size.argtypes = [vp]
+        L.cssar_batch_workspace_size.restype = ctypes.c_size_t
+        L.cssar_batch_set_graph.argtypes = [vp, i]
+        L.cssar_batch_autotune.argtypes = [vp, vp, ctypes.c_char_p, vp]
+        L.cssar_batch_describe.argtypes = [vp, ctypes.c_char_p, i]
+        L.cssar_ita_solve_batched.argtypes = [vp, pp, pp, ctypes.POINTER(f), i, pp, vp, vp]
         for name in ("cssar_make_operator", "cssar_destroy_operator", "cssar_apply_G",
                      "cssar_apply_GH", "cssar_pack_mask", "cssar_ita_solve",
                      "cssar_sync_status", "cssar_supported_length", "cssar_plan_info",
-                     "cssar_profile_enable", "cssar_profile_read"):
+                     "cssar_profile_enable", "cssar_profile_read", "cssar_make_batch",
+                     "cssar_destroy_batch", "cssar_batch_set_graph", "cssar_batch_autotune",
+                     "cssar_batch_describe", "cssar_ita_solve_batched"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -226,3 +240,79 @@ class Operator:
 
 def make_operator(params, shape):
     return Operator(params, shape)
+
+
+def _ptrs(ts):
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+class Batch:
+    """Many scenes solved together (cssar_make_batch): grouped pass kernels
+    per line length, optional HIP-graph replay, measuring autotuner.  Keeps
+    references to its operators (they must outlive it)."""
+
+    def __init__(self, ops):
+        self.ops = list(ops)
+        if not self.ops:
+            raise ValueError("need at least one operator")
+        arr = (ctypes.c_void_p * len(self.ops))(*[op.handle.value for op in self.ops])
+        h = ctypes.c_void_p()
+        _check(lib().cssar_make_batch(arr, len(self.ops), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cssar_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_size(self):
+        return int(lib().cssar_batch_workspace_size(self._h))
+
+    def workspace(self, device=None):
+        return torch.empty(max(self.workspace_size(), 8), dtype=torch.uint8,
+                           device=device or "cuda")
+
+    def set_graph(self, on):
+        _check(lib().cssar_batch_set_graph(self._h, 1 if on else 0))
+
+    def autotune(self, ws=None, cache_path=None):
+        ws = self.workspace() if ws is None else ws
+        if ws.numel() * ws.element_size() < self.workspace_size() or not ws.is_cuda:
+            raise ValueError("workspace too small")
+        cp = cache_path.encode() if cache_path else None
+        _check(lib().cssar_batch_autotune(self._h, _ptr(ws), cp, _stream()))
+
+    def describe(self):
+        n = lib().cssar_batch_describe(self._h, None, 0)
+        buf = ctypes.create_string_buffer(max(n, 0) + 1)
+        lib().cssar_batch_describe(self._h, buf, len(buf))
+        return buf.value.decode()
+
+    def ita_solve(self, ys, mask_bits, lams, iters, outs=None, ws=None):
+        """Iterative thresholding of every scene; returns the list of X^(iters)."""
+        if not (len(ys) == len(mask_bits) == len(lams) == len(self.ops)):
+            raise ValueError("one y, mask and lambda per scene")
+        ys = [op._arr(y, "y") for op, y in zip(self.ops, ys)]
+        for m in mask_bits:
+            if m.dtype != torch.int32 or not m.is_cuda:
+                raise TypeError("mask_bits must come from pack_mask")
+        outs = [torch.empty_like(y) for y in ys] if outs is None else \
+            [op._arr(o, "out") for op, o in zip(self.ops, outs)]
+        if ws is None:
+            ws = self.workspace(ys[0].device)
+        elif ws.numel() * ws.element_size() < self.workspace_size() or not ws.is_cuda:
+            raise ValueError("workspace too small")
+        lam = (ctypes.c_float * len(lams))(*[float(v) for v in lams])
+        _check(lib().cssar_ita_solve_batched(self._h, _ptrs(ys), _ptrs(mask_bits), lam,
+                                             int(iters), _ptrs(outs), _ptr(ws), _stream()))
+        return outs
+
+
+def make_batch(ops):
+    return Batch(ops)

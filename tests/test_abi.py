@@ -99,6 +99,20 @@ def test_null_arguments(L):
     assert L.cssar_sync_status(None, None) == -1
     assert L.cssar_destroy_operator(None) == 0
     assert L.cssar_workspace_size(None, 1) == 0
+    # batch entry points
+    hb = ctypes.c_void_p()
+    assert L.cssar_make_batch(None, 1, ctypes.byref(hb)) == -1
+    ops = (ctypes.c_void_p * 2)(None, None)
+    assert L.cssar_make_batch(ops, 2, ctypes.byref(hb)) == -1
+    assert L.cssar_make_batch(ops, 0, ctypes.byref(hb)) == -1
+    assert L.cssar_make_batch(ops, 2, None) == -1
+    assert hb.value is None
+    assert L.cssar_destroy_batch(None) == 0
+    assert L.cssar_batch_workspace_size(None) == 0
+    assert L.cssar_batch_set_graph(None, 1) == -1
+    assert L.cssar_batch_autotune(None, None, None, None) == -1
+    assert L.cssar_batch_describe(None, None, 0) == -1
+    assert L.cssar_ita_solve_batched(None, None, None, None, 3, None, None, None) == -1
 
 
 def test_binding_refuses_cpu_tensors():
