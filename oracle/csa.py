@@ -67,36 +67,43 @@ class Geometry:
         else:
             self.Km = np.full(na, p["Kr"], dtype=np.float64)
 
-    # -- phase screens (each [N_a, N_r], unit modulus) ---------------------
-    def phi1(self):
+    # -- phase arguments (radians, each [N_a, N_r]) ------------------------
+    def arg1(self):
         """Chirp scaling, range-Doppler domain:
-        exp(i pi Km (D_ref/D - 1) (tau - 2 r_ref / (c D))^2)."""
+        pi Km (D_ref/D - 1) (tau - 2 r_ref / (c D))^2."""
         D = self.D[:, None]
         Km = self.Km[:, None]
         tref = 2.0 * self.p["r_ref"] / (C_LIGHT * D)
-        arg = np.pi * Km * (self.D_ref / D - 1.0) * (self.tau[None, :] - tref) ** 2
-        return np.exp(1j * arg)
+        return np.pi * Km * (self.D_ref / D - 1.0) * (self.tau[None, :] - tref) ** 2
 
-    def phi2(self):
+    def arg2(self):
         """Range compression + SRC + bulk RCMC, 2-D frequency domain:
-        exp(i pi D/(Km D_ref) f_tau^2) exp(i 4 pi r_ref f_tau (1/D - 1/D_ref)/c)."""
+        pi D/(Km D_ref) f_tau^2 + 4 pi r_ref f_tau (1/D - 1/D_ref)/c."""
         D = self.D[:, None]
         Km = self.Km[:, None]
         f = self.f_tau[None, :]
-        arg = (np.pi * D / (Km * self.D_ref) * f ** 2
-               + 4.0 * np.pi * self.p["r_ref"] * f * (1.0 / D - 1.0 / self.D_ref) / C_LIGHT)
-        return np.exp(1j * arg)
+        return (np.pi * D / (Km * self.D_ref) * f ** 2
+                + 4.0 * np.pi * self.p["r_ref"] * f * (1.0 / D - 1.0 / self.D_ref) / C_LIGHT)
 
-    def phi3(self):
+    def arg3(self):
         """Azimuth compression + residual phase, range-Doppler domain:
-        exp(i 4 pi fc R0 D / c) exp(-i 4 pi Km/c^2 (1 - D/D_ref) (R0 - r_ref)^2 / D^2)."""
+        4 pi fc R0 D / c - 4 pi Km/c^2 (1 - D/D_ref) (R0 - r_ref)^2 / D^2."""
         D = self.D[:, None]
         Km = self.Km[:, None]
         r0 = self.r0[None, :]
-        arg = (4.0 * np.pi * self.p["fc"] * r0 * D / C_LIGHT
-               - 4.0 * np.pi * Km / C_LIGHT ** 2 * (1.0 - D / self.D_ref)
-               * (r0 - self.p["r_ref"]) ** 2 / D ** 2)
-        return np.exp(1j * arg)
+        return (4.0 * np.pi * self.p["fc"] * r0 * D / C_LIGHT
+                - 4.0 * np.pi * Km / C_LIGHT ** 2 * (1.0 - D / self.D_ref)
+                * (r0 - self.p["r_ref"]) ** 2 / D ** 2)
+
+    # -- phase screens (each [N_a, N_r], unit modulus) ---------------------
+    def phi1(self):
+        return np.exp(1j * self.arg1())
+
+    def phi2(self):
+        return np.exp(1j * self.arg2())
+
+    def phi3(self):
+        return np.exp(1j * self.arg3())
 
     def screens(self):
         """(Phi1, Phi2, Phi3), computed once and cached."""
