@@ -157,6 +157,46 @@ def bench_batched(steps, iters, device):
     }
 
 
+def bench_grad(steps, device):
+    """Differentiated workload (1024 x 1024, K = 20, checkpoint every 5):
+    forward with checkpoints + reverse pass, against the plain K-iteration
+    solve on the same inputs."""
+    import numpy as np
+    import torch
+    import inputs
+    import paper_1302_3120_amd as pk
+    wl = inputs.workload("grad_1024")
+    shape, K, every = wl["shape"], wl["iters"], wl["every"]
+    op = pk.make_operator(inputs.RADAR_STRIPMAP, shape)
+    g = torch.Generator(device=device)
+    g.manual_seed(wl["seed"])
+    y = torch.randn(*shape, dtype=torch.complex64, generator=g, device=device)
+    m = torch.rand(*shape, generator=g, device=device) < wl["mask_rate"]
+    y = torch.where(m, y, torch.zeros_like(y))
+    bits = op.pack_mask(m)
+    lam = float(torch.quantile(op.apply_GH(y).abs().flatten()[: 1 << 20], 0.99))
+    gx = torch.randn(*shape, dtype=torch.complex64, generator=g, device=device)
+    out = torch.empty_like(y)
+    ws = op.workspace(1, device)
+
+    def plain():
+        op.ita_solve(y, bits, lam, K, out=out, ws=ws)
+
+    def fwd_bwd():
+        _, ck = op.ita_forward(y, bits, lam, K, every)
+        op.ita_backward(y, bits, lam, K, every, ck, gx)
+
+    t_plain = time_steps(plain, steps, 1)
+    t_grad = time_steps(fwd_bwd, steps, 1)
+    return {
+        "workload": f"grad_1024: {shape[0]}x{shape[1]}, K = {K} unrolled iterations, checkpoint "
+                    f"every {every}; gradients in y, lambda, K_a, K_r",
+        "forward_backward_ms": 1e3 * t_grad / steps, "plain_solve_ms": 1e3 * t_plain / steps,
+        "cost_vs_plain_solve": t_grad / t_plain,
+        "iterations_per_s_forward_backward": steps * K / t_grad,
+    }
+
+
 def time_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -316,6 +356,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-scene batched-versus-plain-loop measurement")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the differentiated (forward + reverse pass) measurement")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the event-instrumented region (plain timing only)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -412,6 +454,9 @@ def main():
 
     if not args.no_batched:
         rec["batched"] = bench_batched(3, args.iters, dev)
+
+    if not args.no_grad:
+        rec["differentiated"] = bench_grad(5, dev)
 
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host (one iteration)")

@@ -175,6 +175,42 @@ int cssar_ita_solve_batched(cssar_batch* b, const void* const* ys, const void* c
                             const float* lambdas, int iters, void* const* x_outs, void* ws,
                             void* stream);
 
+/* ------------------------------------------------------------- gradient --
+ * Derivatives of a loss L(X^(K)) of K unrolled iterations of eq. (th2d) /
+ * Algorithm 1 (X^(0) = 0, mu = 1) with respect to the raw data y, the
+ * threshold lambda and the radar parameters K_a = 2 v^2 / (lambda_w r_ref)
+ * (the azimuth FM rate at the reference range, Section II.A) and K_r.  Not
+ * in the paper: plain calculus on the iteration, using G^H = M (Theorem 1)
+ * for the adjoints of the operators.  Convention: for a complex array the
+ * gradient is dL/dRe + i dL/dIm (what torch returns for a real loss). */
+
+/* Bytes of the checkpoint buffer of cssar_ita_forward: one blocked array
+ * (cssar_workspace_size(op, 0)) per iterate X^(c every), 0 < c every < iters.
+ * 0 for NULL or non-positive arguments. */
+size_t cssar_checkpoint_size(const cssar_op* op, int iters, int every);
+
+/* Workspace bytes of cssar_ita_backward: every + 4 blocked arrays. */
+size_t cssar_grad_workspace_size(const cssar_op* op, int every);
+
+/* cssar_ita_solve that also stores the azimuth spectra of the iterates
+ * X^(every), X^(2 every), ... (before the last) in ckpt (device,
+ * cssar_checkpoint_size bytes; may be NULL if that is 0).  x_out equals
+ * cssar_ita_solve's bit for bit.  ws: cssar_workspace_size(op, 1) bytes. */
+int cssar_ita_forward(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters,
+                      int every, void* x_out, void* ckpt, void* ws, void* stream);
+
+/* Reverse pass: given grad_x = dL/dX^(K) (N_a x N_r complex64, row-major)
+ * and the checkpoints of cssar_ita_forward with the same y, mask, lambda,
+ * iters and every, writes grad_y = dL/dy (row-major complex64; zero off the
+ * mask) and grad_scalars (device, 3 doubles) = (dL/dlambda, dL/dK_a,
+ * dL/dK_r).  Each checkpoint segment is recomputed once.  ws:
+ * cssar_grad_workspace_size(op, every) bytes.  grad_y must not alias y,
+ * grad_x or ws.  The operator's partial-sum buffer is used: calls sharing
+ * an operator must be ordered on one stream. */
+int cssar_ita_backward(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters,
+                       int every, const void* ckpt, const void* grad_x, void* grad_y,
+                       double* grad_scalars, void* ws, void* stream);
+
 /* Synchronise the stream and report a deferred device-side error of this
  * operator (CSSAR_ENONFINITE if a residual norm was NaN/Inf), clearing it. */
 int cssar_sync_status(cssar_op* op, void* stream);
@@ -189,8 +225,11 @@ const char* cssar_last_error(void);
  * 0 row pass of M (Phi1, range FFT, Phi2, inverse, Phi3), 1 row pass of G
  * (conjugate screens, reverse order), 2 column forward azimuth FFT (with
  * optional mask and residual norm), 3 column inverse azimuth FFT, 4 column
- * update + soft-threshold pass, 5 column residual pass; 6 and 7 unused. */
-#define CSSAR_PROFILE_KINDS 8
+ * update + soft-threshold pass, 5 column residual pass, 6 column threshold
+ * adjoint, 7 column data adjoint, 8 column iterate adjoint, 9 adjoint row
+ * pass with M forward, 10 adjoint row pass with G forward, 11 unused.
+ * ms_sum and counts hold CSSAR_PROFILE_KINDS entries. */
+#define CSSAR_PROFILE_KINDS 12
 int cssar_profile_enable(cssar_op* op, int on);
 int cssar_profile_read(cssar_op* op, double* ms_sum, long* counts);
 

@@ -176,6 +176,10 @@ int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
   return timed(op, 2 + which, s, [&] { return op->ka->col[which](a, op->grid_col[which], s); });
 }
 
+int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s) {
+  return timed(op, 9 + conj, s, [&] { return op->kr->row_adj[conj](a, op->grid_adj[conj], s); });
+}
+
 }  // namespace detail
 }  // namespace cssar
 
@@ -231,8 +235,11 @@ int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** ou
     return cleanup(fail(CSSAR_EHIP, "cannot query the compute unit count"));
   const size_t rowb = sizeof(double2) * n_az;
   void* mem = nullptr;
+  std::vector<float> rd;
+  build_derivatives(*p, n_az, n_rg, rd);
   const size_t total = 3 * rowb + sizeof(float2) * (n_az + n_rg) +
-                       sizeof(float) * kMaxPartials + 4 * sizeof(unsigned) + 1024;
+                       sizeof(float) * kMaxPartials + 4 * sizeof(unsigned) + 256 +
+                       sizeof(float) * rd.size() + 1024;
   if (hipMalloc(&mem, total) != hipSuccess) return cleanup(fail(CSSAR_ENOMEM, "hipMalloc of %zu bytes failed", total));
   char* base = (char*)mem;
   op->rowc1 = (double2*)base;
@@ -242,17 +249,21 @@ int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** ou
   op->tw_r = op->tw_a + n_az;
   op->partials = (float*)(op->tw_r + n_rg);
   op->counter = (unsigned*)(op->partials + kMaxPartials);
+  op->rowd = (float*)((char*)op->counter + 256);
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemcpy(op->rowc1, r1.data(), rowb, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(op->rowc2, r2.data(), rowb, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(op->rowc3, r3.data(), rowb, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(op->tw_a, ta.data(), sizeof(float2) * n_az, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(op->tw_r, tr.data(), sizeof(float2) * n_rg, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(op->rowd, rd.data(), sizeof(float) * rd.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(op->counter, 0, 4 * sizeof(unsigned));
   if (e != hipSuccess) return cleanup(fail(CSSAR_EHIP, "uploading operator tables: %s", hipGetErrorString(e)));
 
   const int row_work = (n_az + kr->LR - 1) / kr->LR;
   op->grid_row = grid_for(row_work, op->cus, occupancy(kr->row_fn, kr->RT));
+  for (int c = 0; c < 2; ++c)
+    op->grid_adj[c] = std::min(grid_for(row_work, op->cus, occupancy(kr->row_adj_fn[c], kr->RT)), kMaxPartials / 2);
   const int col_work = n_rg / ka->C;
   for (int w = 0; w < CK_COUNT; ++w) {
     op->grid_col[w] = grid_for(col_work, op->cus, occupancy(ka->col_fn[w], ka->CT));

@@ -51,8 +51,10 @@ struct cssar_op {
   float2* tw_r = nullptr;           // w_{N_r}^k
   float* partials = nullptr;        // per-block partial sums
   unsigned* counter = nullptr;      // [0] last-block counter, [1] status bits
+  float* rowd = nullptr;            // per Doppler bin: 18 screen-derivative coefficients
   int grid_row = 0;
   int grid_col[cssar::CK_COUNT] = {};
+  int grid_adj[2] = {};
   // optional per-launch HIP event timing (cssar_profile_enable)
   bool profiling = false;
   struct Rec {
@@ -69,6 +71,16 @@ namespace detail {
 ColArgs col_args(const cssar_op* op);
 RowArgs row_args(const cssar_op* op, const void* in, void* out, int conj);
 int check_op(const cssar_op* op);
+
+// Launch a pass kernel of the operator (timed when profiling is on).
+int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s);
+int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s);
+int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s);
+
+// Per Doppler bin, the derivatives of the three phase arguments (radians)
+// with respect to K_a and K_r as polynomials of the centred column offset
+// (Phi1, Phi3) or the signed range bin (Phi2): 18 floats per bin.
+void build_derivatives(const cssar_params& p, int na, int nr, std::vector<float>& out);
 
 }  // namespace detail
 }  // namespace cssar

@@ -71,21 +71,33 @@ struct RowArgs {
   double inv_fs;         // 1 / fs
   double fc_fs;          // fc / fs
   double p_c;            // fc * 2 r_ref / c (Phi3 turns per unit D at the reference range)
+  // adjoint row pass only
+  const float2* in2;     // input of the adjoint chain (B4)
+  const float* rowd;     // per Doppler bin: 18 floats, d arg_k / d theta as
+                         // polynomials c0 + c1 o + c2 o^2 (radians), ordered
+                         // [theta = K_a, K_r][stage 1, 2, 3][c0, c1, c2]
+  float* partials;       // per-block partial sums (2 per block)
 };
 
-enum ColMode { COL_FWD = 0, COL_INV = 1, COL_A = 2, COL_R = 3 };
+// Column modes.  FWD, INV, A, R: the forward passes.  VB, U, XB: the
+// adjoint passes of the gradient (threshold adjoint, data adjoint, update
+// of the iterate's adjoint).
+enum ColMode { COL_FWD = 0, COL_INV = 1, COL_A = 2, COL_R = 3, COL_VB = 4, COL_U = 5, COL_XB = 6 };
 
 // Marks an unsampled entry of the stored copy of m o y (real part; a NaN
 // with a payload that arithmetic does not produce).
 constexpr uint32_t kUnsampled = 0x7FA5A5A5u;
 
 struct ColArgs {
-  const float2* in0;     // FWD: input (RM); INV: input (B4); A: Xt (B4, NULL on the first iteration); R: W (B4)
-  const float2* in1;     // A: Z (B4)
-  const float2* y;       // R: m o y (B4), unsampled entries marked with kUnsampled
+  const float2* in0;     // FWD: input (RM); INV: input (B4); A, VB: Xt (B4, NULL on the first
+                         // iteration); R: W (B4); U: F G Vbar; XB: F M ubar
+  const float2* in1;     // A, VB: Z (B4); U: ybar accumulator (spatial); XB: Vbar (spatial)
+  const float2* y;       // R, U: m o y (B4), unsampled entries marked with kUnsampled;
+                         // VB: adjoint of the next iterate (spatial)
   const uint32_t* mask;  // FWD: packed sampling mask, bit = blocked element index
   float2* out;           // FWD, R: B4; INV: RM; A: B4, or RM with flag 2
-  float2* out2;          // FWD with flag 4: copy of m o y (B4, marked)
+  float2* out2;          // FWD with flag 4: copy of m o y (B4, marked); VB: Vbar (spatial);
+                         // U: ybar accumulator (spatial, may alias in1)
   const float2* tw;      // w_N^k, N = N_a
   int na, nr;
   int flags;             // FWD: 1 = mask the input and sum |.|^2, 4 = write out2;
@@ -267,6 +279,113 @@ __global__ __launch_bounds__(P::RT) void row_group_kernel(GroupArgs g) {
   }
 }
 
+// ------------------------------------------------------ adjoint row pass --
+// One unit of the adjoint row pass.  The forward chain (M for CONJ = 0, G
+// for CONJ = 1) runs on the line of a.in; the opposite chain, which is its
+// adjoint (Theorem 1: G = M^H, stage by stage), runs on the line of a.in2
+// and is written to a.out.  At each phase stage k the derivative of the
+// screen, +-i (d arg_k/d theta) exp(+-i arg_k), pairs the forward value
+// a_k with the adjoint value w_k at that point:
+//   d/d theta contributes  s Re(conj(w_k) i arg_k' a_k) = s arg_k' (w.y a.x - w.x a.y),
+// s = +1 for M's screens, -1 for G's conjugate screens.  Because the
+// screens are unimodular the product may be taken on either side of the
+// screen: stage 1 pairs the forward input with the adjoint output, stage 3
+// the forward value before its last screen with the adjoint value after its
+// first, and stage 2 the two values in the 2-D frequency domain.  Products
+// carry the factor N_a of the unnormalised azimuth spectra, removed when the
+// partial sums are reduced.
+__device__ __forceinline__ float dpoly(const float* c, float o) { return fmaf(fmaf(c[2], o, c[1]), o, c[0]); }
+
+template <int E, int T, bool FREQ>
+__device__ __forceinline__ void pair_stage(const float2 (&f)[E], const float2 (&w)[E], const float* dka,
+                                           const float* dkr, int b, float sgn, float& acc_ka, float& acc_kr) {
+  float cka[3], ckr[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    cka[i] = dka[i];
+    ckr[i] = dkr[i];
+  }
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int kk = FREQ ? (k < E / 2 ? k : k - E) : k - E / 2;
+    const float o = (float)(b + T * kk);
+    const float cr = sgn * (w[k].y * f[k].x - w[k].x * f[k].y);
+    acc_ka = fmaf(dpoly(cka, o), cr, acc_ka);
+    acc_kr = fmaf(dpoly(ckr, o), cr, acc_kr);
+  }
+}
+
+template <class P, int CONJ>
+__device__ __forceinline__ void row_adj_unit(const RowArgs& a, int gi, const RowLane<P>& ln, float2* lds,
+                                             const float2* twl, float& acc_ka, float& acc_kr) {
+  constexpr int N = P::N, E = P::E, T = P::T, LR = P::LR;
+  constexpr int LI = RowLds<P>::LI, LS = RowLds<P>::LS;
+  const uint32_t S = b4_stride(N);
+  const uint32_t bytes = clamp_bytes(b4_bytes(a.na, N));
+  const Buf in(a.in, bytes), in2(a.in2, bytes), out(a.out, bytes);
+  constexpr bool cj = CONJ != 0;
+  constexpr float sgn = cj ? -1.0f : 1.0f;
+  const int b = ln.b, line = ln.line;
+  const int row = gi * LR + line;
+  const uint32_t vo = (uint32_t)(row >> 2) * S + (uint32_t)(b >> 2) * 128u + (uint32_t)(row & 3) * 32u +
+                      (uint32_t)(b & 3) * 8u;
+  const double2 c1 = a.rowc1[row], c2 = a.rowc2[row], c3 = a.rowc3[row];
+  const float* d = a.rowd + (size_t)row * 18;  // [theta][stage][coefficient]
+  // stage index (0: arg1, 1: arg2, 2: arg3) of the forward chain's first and last screens
+  constexpr int s_first = cj ? 2 : 0, s_last = cj ? 0 : 2;
+  int lb = b, lc = line % LI;
+  asm volatile("" : "+v"(lb), "+v"(lc));
+  float2* lmy = lds + (line / LI) * LS;
+  asm volatile("" : "+v"(lmy));
+  const TwLds tws{twl, twl + 64};
+  float2 x0[E], f[E], fm[E], w[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) x0[k] = in.f2(vo, T * k * 32);
+  // forward chain up to its last screen
+#pragma unroll
+  for (int k = 0; k < E; ++k) f[k] = x0[k];
+  apply_quad<E, false>(f, cj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), cj, 1.0f);
+  fft_line<P, false, LI>(f, lb, lc, lmy, tws);
+  apply_quad<E, true>(f, phi2_quad(c2, b, T), cj, a.scale);
+#pragma unroll
+  for (int k = 0; k < E; ++k) fm[k] = f[k];
+  asm volatile("" : "+v"(lb), "+v"(lc), "+v"(lmy));
+  fft_line<P, true, LI>(f, lb, lc, lmy, tws);
+  // adjoint chain: its first screen is the conjugate of the forward's last
+#pragma unroll
+  for (int k = 0; k < E; ++k) w[k] = in2.f2(vo, T * k * 32);
+  apply_quad<E, false>(w, cj ? phi1_quad(c1, a, b, T) : phi3_quad(c3, a, b, T), !cj, 1.0f);
+  pair_stage<E, T, false>(f, w, d + s_last * 3, d + 9 + s_last * 3, b, sgn, acc_ka, acc_kr);
+  asm volatile("" : "+v"(lb), "+v"(lc), "+v"(lmy));
+  fft_line<P, false, LI>(w, lb, lc, lmy, tws);
+  pair_stage<E, T, true>(fm, w, d + 3, d + 12, b, sgn, acc_ka, acc_kr);
+  apply_quad<E, true>(w, phi2_quad(c2, b, T), !cj, a.scale);
+  asm volatile("" : "+v"(lb), "+v"(lc), "+v"(lmy));
+  fft_line<P, true, LI>(w, lb, lc, lmy, tws);
+  apply_quad<E, false>(w, cj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), !cj, 1.0f);
+  pair_stage<E, T, false>(x0, w, d + s_first * 3, d + 9 + s_first * 3, b, sgn, acc_ka, acc_kr);
+#pragma unroll
+  for (int k = 0; k < E; ++k) out.st(w[k], vo, T * k * 32);
+}
+
+template <class P, int CONJ>
+__global__ __launch_bounds__(P::RT) void row_adj_kernel(RowArgs a) {
+  __shared__ float2 lds[RowLds<P>::size];
+  __shared__ float2 twl[64 + P::N / 64];
+  __shared__ float red[P::RT / 64];
+  load_twiddle_table<P::N>(twl, a.tw);
+  __syncthreads();
+  const RowLane<P> ln;
+  const int units = a.na / P::LR;
+  float acc_ka = 0.f, acc_kr = 0.f;
+  for (int gi = xcd_logical_block(); gi < units; gi += gridDim.x)
+    row_adj_unit<P, CONJ>(a, gi, ln, lds, twl, acc_ka, acc_kr);
+  const float s0 = block_sum<P::RT>(acc_ka, red);
+  if (threadIdx.x == 0) a.partials[2 * blockIdx.x] = s0;
+  const float s1 = block_sum<P::RT>(acc_kr, red);
+  if (threadIdx.x == 0) a.partials[2 * blockIdx.x + 1] = s1;
+}
+
 // ---------------------------------------------------------- column pass --
 // One tile (C adjacent columns) of a column pass of array a.  Returns the
 // thread's share of the tile's squared norm (FWD with the mask, R).
@@ -279,13 +398,14 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
   const int out_layout = (MODE == COL_INV || (MODE == COL_A && (a.flags & 2))) ? RM : B4;
   const Buf in0(a.in0, in_layout == RM ? rmb : b4b), in1(a.in1, b4b), yb(a.y, b4b);
   const Buf out(a.out, out_layout == RM ? rmb : b4b), out2(a.out2, b4b);
-  const bool first = (MODE == COL_A) && (a.flags & 1);
+  const bool first = (MODE == COL_A || MODE == COL_VB) && (a.flags & 1);
   const int j = tile * C + c;
   const Addr ai = col_addr(in_layout, b, j, T, a.nr);
   const Addr ab = col_addr(B4, b, j, T, a.nr);
   float acc = 0.f;
   float2 v[E], y2[E];
-  if constexpr (MODE == COL_A) {
+  float2 y3[(MODE == COL_VB || MODE == COL_U || MODE == COL_XB) ? E : 1];
+  if constexpr (MODE == COL_A || MODE == COL_VB) {
     // V = F^-1[Xt + mu Z] / N_a
     const float ms = a.mu * a.scale;
 #pragma unroll
@@ -297,15 +417,23 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
         v[k] = make_float2(fmaf(a.scale, x.x, v[k].x), fmaf(a.scale, x.y, v[k].y));
       }
     }
+    if constexpr (MODE == COL_VB) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) y3[k] = yb.f2(ab.voff, k * ab.kstep);  // Xbar of X+
+    }
   } else if constexpr (MODE == COL_FWD) {
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = in0.f2(ai.voff, k * ai.kstep);
   } else {
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = cscale(in0.f2(ai.voff, k * ai.kstep), a.scale);
-    if constexpr (MODE == COL_R) {
+    if constexpr (MODE == COL_R || MODE == COL_U) {
 #pragma unroll
       for (int k = 0; k < E; ++k) y2[k] = yb.f2(ab.voff, k * ab.kstep);
+    }
+    if constexpr (MODE == COL_U || MODE == COL_XB) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) y3[k] = in1.f2(ab.voff, k * ab.kstep);
     }
   }
   const TwLds tws{twl, twl + 64};
@@ -345,6 +473,48 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
       asm volatile("" : "+v"(lb), "+v"(lc));
       fft_line<P, false, C>(v, lb, lc, lds, tws);  // Xt+ = F X+
     }
+  } else if constexpr (MODE == COL_VB) {
+    // Vbar = J_S(V)^T Xbar (the threshold's real Jacobian, symmetric):
+    // on |V| > sigma, (1 - sigma/|V|) Xbar + sigma Re(conj(V) Xbar) V / |V|^3;
+    // d X+ / d sigma = -V/|V| gives the partial -Re(conj(V) Xbar)/|V|.
+    // The support test is the update pass's, on the same V.
+    fft_line<P, true, C>(v, lb, lc, lds, tws);
+    const float s2 = a.sigma * a.sigma;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const float m2 = fmaf(v[k].x, v[k].x, v[k].y * v[k].y);
+      const float2 xb = y3[k];
+      float2 vb = make_float2(0.f, 0.f);
+      if (m2 > s2) {
+        const float inv = rsqrtf(m2);
+        const float dot = fmaf(v[k].x, xb.x, v[k].y * xb.y);
+        const float f = fmaf(-a.sigma, inv, 1.0f);
+        const float g = a.sigma * dot * inv * inv * inv;
+        vb = make_float2(fmaf(f, xb.x, g * v[k].x), fmaf(f, xb.y, g * v[k].y));
+        acc = fmaf(-dot, inv, acc);
+      }
+      out2.st(vb, ab.voff, k * ab.kstep);
+      v[k] = cscale(vb, a.mu);
+    }
+    asm volatile("" : "+v"(lb), "+v"(lc));
+    fft_line<P, false, C>(v, lb, lc, lds, tws);  // F (mu Vbar)
+  } else if constexpr (MODE == COL_U) {
+    // g = F^-1[F G mu Vbar] / N_a; ybar += m o g; ubar = -m o g; out = F ubar
+    fft_line<P, true, C>(v, lb, lc, lds, tws);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const bool keep = __float_as_uint(y2[k].x) != kUnsampled;
+      const float2 g = keep ? v[k] : make_float2(0.f, 0.f);
+      out2.st(cadd(y3[k], g), ab.voff, k * ab.kstep);
+      v[k] = make_float2(-g.x, -g.y);
+    }
+    asm volatile("" : "+v"(lb), "+v"(lc));
+    fft_line<P, false, C>(v, lb, lc, lds, tws);
+  } else if constexpr (MODE == COL_XB) {
+    // Xbar = Vbar + F^-1[F M ubar] / N_a (spatial)
+    fft_line<P, true, C>(v, lb, lc, lds, tws);
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = cadd(y3[k], v[k]);
   } else {  // COL_R: GX = F^-1[W] / N_a; R = m o y - m o GX; out = F R
     fft_line<P, true, C>(v, lb, lc, lds, tws);
 #pragma unroll
@@ -382,6 +552,10 @@ __global__ __launch_bounds__(P::CT) void col_pass_kernel(ColArgs a) {
     const float part = block_sum<CT>(acc, red);
     finish_partials(part, a.partials, a.counter, a.hist_out, a.status, gridDim.x);
   }
+  if constexpr (MODE == COL_VB) {
+    const float part = block_sum<CT>(acc, red);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = part;  // reduced by reduce_partials_kernel
+  }
 }
 
 // Grouped column pass (batched solver): no norms are formed.
@@ -415,6 +589,11 @@ struct Kernels {
   }
   static hipError_t row_group(const GroupArgs& g, int grid, hipStream_t s) {
     hipLaunchKernelGGL(row_group_kernel<P>, dim3(grid), dim3(P::RT), 0, s, g);
+    return hipGetLastError();
+  }
+  template <int CONJ>
+  static hipError_t row_adj(const RowArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((row_adj_kernel<P, CONJ>), dim3(grid), dim3(P::RT), 0, s, a);
     return hipGetLastError();
   }
   template <int MODE>

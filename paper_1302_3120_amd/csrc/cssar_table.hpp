@@ -12,7 +12,9 @@ struct RowArgs;
 struct ColArgs;
 struct GroupArgs;
 
-enum ColKernel { CK_FWD = 0, CK_INV, CK_A, CK_R, CK_COUNT };
+// Column kernels: the first CK_GROUPED also exist as grouped (batched) kernels.
+enum ColKernel { CK_FWD = 0, CK_INV, CK_A, CK_R, CK_VB, CK_U, CK_XB, CK_COUNT };
+constexpr int CK_GROUPED = 4;
 
 struct KernelTable {
   int n, variant, E, T, C, CT, RT, LR, passes;
@@ -20,11 +22,13 @@ struct KernelTable {
   hipError_t (*row)(const RowArgs&, int, hipStream_t);
   hipError_t (*col[CK_COUNT])(const ColArgs&, int, hipStream_t);
   hipError_t (*row_group)(const GroupArgs&, int, hipStream_t);
-  hipError_t (*col_group[CK_COUNT])(const GroupArgs&, int, hipStream_t);
+  hipError_t (*col_group[CK_GROUPED])(const GroupArgs&, int, hipStream_t);
+  hipError_t (*row_adj[2])(const RowArgs&, int, hipStream_t);  // forward chain M (0) or G (1)
   const void* row_fn;
   const void* col_fn[CK_COUNT];
   const void* row_group_fn;
-  const void* col_group_fn[CK_COUNT];
+  const void* col_group_fn[CK_GROUPED];
+  const void* row_adj_fn[2];
 };
 
 #define CSSAR_DECL_TABLE(NN, VV) const KernelTable* kernel_table_##NN##_##VV();

@@ -22,20 +22,27 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
        P::P > 3 ? P::R[3] : 0, P::P > 4 ? P::R[4] : 0, 0, 0, 0},
       &K::row,
       {&K::template col<COL_FWD>, &K::template col<COL_INV>, &K::template col<COL_A>,
-       &K::template col<COL_R>},
+       &K::template col<COL_R>, &K::template col<COL_VB>, &K::template col<COL_U>,
+       &K::template col<COL_XB>},
       &K::row_group,
       {&K::template col_group<COL_FWD>, &K::template col_group<COL_INV>,
        &K::template col_group<COL_A>, &K::template col_group<COL_R>},
+      {&K::template row_adj<0>, &K::template row_adj<1>},
       reinterpret_cast<const void*>(&row_pass_kernel<P>),
       {reinterpret_cast<const void*>(&col_pass_kernel<P, COL_FWD>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_INV>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_A>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_R>)},
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_R>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_VB>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_U>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_XB>)},
       reinterpret_cast<const void*>(&row_group_kernel<P>),
       {reinterpret_cast<const void*>(&col_group_kernel<P, COL_FWD>),
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_INV>),
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_A>),
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_R>)},
+      {reinterpret_cast<const void*>(&row_adj_kernel<P, 0>),
+       reinterpret_cast<const void*>(&row_adj_kernel<P, 1>)},
   };
   return &t;
 }

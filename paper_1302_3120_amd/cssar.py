@@ -26,11 +26,14 @@ SYMBOLS = (
     "cssar_plan_info", "cssar_profile_enable", "cssar_profile_read",
     "cssar_make_batch", "cssar_destroy_batch", "cssar_batch_workspace_size",
     "cssar_batch_set_graph", "cssar_batch_autotune", "cssar_batch_describe",
-    "cssar_ita_solve_batched",
+    "cssar_ita_solve_batched", "cssar_checkpoint_size", "cssar_grad_workspace_size",
+    "cssar_ita_forward", "cssar_ita_backward",
 )
 
 PROFILE_KINDS = ("row_M", "row_G", "col_fwd", "col_inv", "col_update_threshold",
-                 "col_residual", "unused6", "unused7")
+                 "col_residual", "col_threshold_adjoint", "col_data_adjoint",
+                 "col_iterate_adjoint", "row_adjoint_M", "row_adjoint_G", "unused11")
+NK = len(PROFILE_KINDS)
 
 
 class CssarError(RuntimeError):
@@ -80,8 +83,8 @@ def lib():
         L.cssar_plan_info.argtypes = [i, ctypes.POINTER(i), ctypes.POINTER(i),
                                       ctypes.POINTER(i * 8)]
         L.cssar_profile_enable.argtypes = [vp, i]
-        L.cssar_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double * 8),
-                                         ctypes.POINTER(ctypes.c_long * 8)]
+        L.cssar_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double * NK),
+                                         ctypes.POINTER(ctypes.c_long * NK)]
         pp = ctypes.POINTER(vp)
         L.cssar_make_batch.argtypes = [pp, i, pp]
         L.cssar_destroy_batch.argtypes = [vp]
@@ -91,6 +94,14 @@ def lib():
         L.cssar_batch_autotune.argtypes = [vp, vp, ctypes.c_char_p, vp]
         L.cssar_batch_describe.argtypes = [vp, ctypes.c_char_p, i]
         L.cssar_ita_solve_batched.argtypes = [vp, pp, pp, ctypes.POINTER(f), i, pp, vp, vp]
+        L.cssar_checkpoint_size.argtypes = [vp, i, i]
+        L.cssar_checkpoint_size.restype = ctypes.c_size_t
+        L.cssar_grad_workspace_size.argtypes = [vp, i]
+        L.cssar_grad_workspace_size.restype = ctypes.c_size_t
+        L.cssar_ita_forward.argtypes = [vp, vp, vp, f, i, i, vp, vp, vp, vp]
+        L.cssar_ita_backward.argtypes = [vp, vp, vp, f, i, i, vp, vp, vp, vp, vp, vp]
+        L.cssar_ita_forward.restype = ctypes.c_int
+        L.cssar_ita_backward.restype = ctypes.c_int
         for name in ("cssar_make_operator", "cssar_destroy_operator", "cssar_apply_G",
                      "cssar_apply_GH", "cssar_pack_mask", "cssar_ita_solve",
                      "cssar_sync_status", "cssar_supported_length", "cssar_plan_info",
@@ -223,6 +234,35 @@ class Operator:
                                      _ptr(ws), _stream()))
         return (out, hist) if resid else out
 
+    def ita_forward(self, y, mask_bits, lam, iters, every, out=None):
+        """cssar_ita_forward: X^(iters) and the checkpoint buffer for the
+        reverse pass."""
+        y = self._arr(y, "y")
+        if mask_bits.dtype != torch.int32 or not mask_bits.is_cuda:
+            raise TypeError("mask_bits must come from pack_mask")
+        out = torch.empty_like(y) if out is None else self._arr(out, "out")
+        nck = int(lib().cssar_checkpoint_size(self._h, int(iters), int(every)))
+        ckpt = torch.empty(max(nck, 8), dtype=torch.uint8, device=y.device)
+        ws = self.workspace(1, y.device)
+        _check(lib().cssar_ita_forward(self._h, _ptr(y), _ptr(mask_bits), float(lam), int(iters),
+                                       int(every), _ptr(out), _ptr(ckpt) if nck else None,
+                                       _ptr(ws), _stream()))
+        return out, ckpt
+
+    def ita_backward(self, y, mask_bits, lam, iters, every, ckpt, grad_x):
+        """cssar_ita_backward: (dL/dy, tensor([dL/dlambda, dL/dK_a, dL/dK_r]))
+        given dL/dX^(iters)."""
+        y = self._arr(y, "y")
+        grad_x = self._arr(grad_x.contiguous(), "grad_x")
+        gy = torch.empty_like(y)
+        gs = torch.empty(3, dtype=torch.float64, device=y.device)
+        nws = int(lib().cssar_grad_workspace_size(self._h, int(every)))
+        ws = torch.empty(max(nws, 8), dtype=torch.uint8, device=y.device)
+        _check(lib().cssar_ita_backward(self._h, _ptr(y), _ptr(mask_bits), float(lam), int(iters),
+                                        int(every), _ptr(ckpt), _ptr(grad_x), _ptr(gy),
+                                        ctypes.c_void_p(gs.data_ptr()), _ptr(ws), _stream()))
+        return gy, gs
+
     def sync_status(self):
         _check(lib().cssar_sync_status(self._h, _stream()))
 
@@ -232,10 +272,10 @@ class Operator:
 
     def profile_read(self):
         """{kind: (total ms, launches)} since the last read (waits for the events)."""
-        ms = (ctypes.c_double * 8)()
-        cnt = (ctypes.c_long * 8)()
+        ms = (ctypes.c_double * NK)()
+        cnt = (ctypes.c_long * NK)()
         _check(lib().cssar_profile_read(self._h, ctypes.byref(ms), ctypes.byref(cnt)))
-        return {PROFILE_KINDS[k]: (ms[k], cnt[k]) for k in range(8) if cnt[k]}
+        return {PROFILE_KINDS[k]: (ms[k], cnt[k]) for k in range(NK) if cnt[k]}
 
 
 def make_operator(params, shape):
@@ -316,3 +356,47 @@ class Batch:
 
 def make_batch(ops):
     return Batch(ops)
+
+
+C_LIGHT = 299792458.0
+
+
+def ka_of(params):
+    """Azimuth FM rate at the reference range, K_a = 2 v^2 / (lambda_w r_ref)."""
+    return 2.0 * params["v"] ** 2 / ((C_LIGHT / params["fc"]) * params["r_ref"])
+
+
+def params_with_theta(params, Ka, Kr):
+    """params with v set from K_a and the range chirp rate set to K_r."""
+    p = dict(params)
+    p["v"] = (Ka * (C_LIGHT / p["fc"]) * p["r_ref"] / 2.0) ** 0.5
+    p["Kr"] = float(Kr)
+    return p
+
+
+class ITAUnrolled(torch.autograd.Function):
+    """X^(K) of K unrolled iterations as a differentiable function of the
+    raw data y (complex64), lambda, K_a and K_r (0-dim float64 tensors).
+    Forward: cssar_ita_forward with a checkpoint every ``every`` iterations;
+    backward: cssar_ita_backward.  The operator is rebuilt from (K_a, K_r)."""
+
+    @staticmethod
+    def forward(ctx, y, lam, Ka, Kr, mask, iters, every, params):
+        p = params_with_theta(params, float(Ka), float(Kr))
+        op = Operator(p, tuple(y.shape))
+        bits = op.pack_mask(mask)
+        x, ckpt = op.ita_forward(y.contiguous(), bits, float(lam), int(iters), int(every))
+        ctx.op, ctx.bits, ctx.ckpt = op, bits, ckpt
+        ctx.args = (float(lam), int(iters), int(every))
+        ctx.meta = [(t.device, t.dtype) if isinstance(t, torch.Tensor) else None for t in (lam, Ka, Kr)]
+        ctx.save_for_backward(y)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (y,) = ctx.saved_tensors
+        lam, iters, every = ctx.args
+        gy, gs = ctx.op.ita_backward(y.contiguous(), ctx.bits, lam, iters, every, ctx.ckpt, gx)
+        scal = [gs[i].to(device=m[0], dtype=m[1]) if m is not None else None
+                for i, m in enumerate(ctx.meta)]
+        return (gy, *scal, None, None, None, None)

@@ -113,6 +113,11 @@ def test_null_arguments(L):
     assert L.cssar_batch_autotune(None, None, None, None) == -1
     assert L.cssar_batch_describe(None, None, 0) == -1
     assert L.cssar_ita_solve_batched(None, None, None, None, 3, None, None, None) == -1
+    # gradient entry points
+    assert L.cssar_checkpoint_size(None, 10, 5) == 0
+    assert L.cssar_grad_workspace_size(None, 5) == 0
+    assert L.cssar_ita_forward(None, None, None, 0.1, 10, 5, None, None, None, None) == -1
+    assert L.cssar_ita_backward(None, None, None, 0.1, 10, 5, None, None, None, None, None, None) == -1
 
 
 def test_binding_refuses_cpu_tensors():
