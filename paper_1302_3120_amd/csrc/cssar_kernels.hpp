@@ -238,15 +238,17 @@ __device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane
   const double2 c1 = a.rowc1[row], c2 = a.rowc2[row], c3 = a.rowc3[row];
   int lb = b, lc = line % LI;
   asm volatile("" : "+v"(lb), "+v"(lc));  // recompute LDS addresses per unit (register pressure)
-  float2* lmy = lds + (line / LI) * LS;
-  asm volatile("" : "+v"(lmy));
+  // the LDS line offset is kept opaque (register pressure) as an integer, so
+  // the compiler still knows lds + loff is in LDS (DS, not FLAT, accesses)
+  int loff = (line / LI) * LS;
+  asm volatile("" : "+v"(loff));
   const TwLds tws{twl, twl + 64};
   // first range-Doppler screen: Phi1 (M) or Phi3* (G)
   apply_quad<E, false>(v, conj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), conj, 1.0f);
-  fft_line<P, false, LI>(v, lb, lc, lmy, tws);
+  fft_line<P, false, LI>(v, lb, lc, lds + loff, tws);
   apply_quad<E, true>(v, phi2_quad(c2, b, T), conj, a.scale);
-  asm volatile("" : "+v"(lb), "+v"(lc), "+v"(lmy));
-  fft_line<P, true, LI>(v, lb, lc, lmy, tws);
+  asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
+  fft_line<P, true, LI>(v, lb, lc, lds + loff, tws);
   // second range-Doppler screen: Phi3 (M) or Phi1* (G)
   apply_quad<E, false>(v, conj ? phi1_quad(c1, a, b, T) : phi3_quad(c3, a, b, T), conj, 1.0f);
 #pragma unroll
@@ -335,8 +337,10 @@ __device__ __forceinline__ void row_adj_unit(const RowArgs& a, int gi, const Row
   constexpr int s_first = cj ? 2 : 0, s_last = cj ? 0 : 2;
   int lb = b, lc = line % LI;
   asm volatile("" : "+v"(lb), "+v"(lc));
-  float2* lmy = lds + (line / LI) * LS;
-  asm volatile("" : "+v"(lmy));
+  // the LDS line offset is kept opaque (register pressure) as an integer, so
+  // the compiler still knows lds + loff is in LDS (DS, not FLAT, accesses)
+  int loff = (line / LI) * LS;
+  asm volatile("" : "+v"(loff));
   const TwLds tws{twl, twl + 64};
   float2 x0[E], f[E], fm[E], w[E];
 #pragma unroll
@@ -345,23 +349,23 @@ __device__ __forceinline__ void row_adj_unit(const RowArgs& a, int gi, const Row
 #pragma unroll
   for (int k = 0; k < E; ++k) f[k] = x0[k];
   apply_quad<E, false>(f, cj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), cj, 1.0f);
-  fft_line<P, false, LI>(f, lb, lc, lmy, tws);
+  fft_line<P, false, LI>(f, lb, lc, lds + loff, tws);
   apply_quad<E, true>(f, phi2_quad(c2, b, T), cj, a.scale);
 #pragma unroll
   for (int k = 0; k < E; ++k) fm[k] = f[k];
-  asm volatile("" : "+v"(lb), "+v"(lc), "+v"(lmy));
-  fft_line<P, true, LI>(f, lb, lc, lmy, tws);
+  asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
+  fft_line<P, true, LI>(f, lb, lc, lds + loff, tws);
   // adjoint chain: its first screen is the conjugate of the forward's last
 #pragma unroll
   for (int k = 0; k < E; ++k) w[k] = in2.f2(vo, T * k * 32);
   apply_quad<E, false>(w, cj ? phi1_quad(c1, a, b, T) : phi3_quad(c3, a, b, T), !cj, 1.0f);
   pair_stage<E, T, false>(f, w, d + s_last * 3, d + 9 + s_last * 3, b, sgn, acc_ka, acc_kr);
-  asm volatile("" : "+v"(lb), "+v"(lc), "+v"(lmy));
-  fft_line<P, false, LI>(w, lb, lc, lmy, tws);
+  asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
+  fft_line<P, false, LI>(w, lb, lc, lds + loff, tws);
   pair_stage<E, T, true>(fm, w, d + 3, d + 12, b, sgn, acc_ka, acc_kr);
   apply_quad<E, true>(w, phi2_quad(c2, b, T), !cj, a.scale);
-  asm volatile("" : "+v"(lb), "+v"(lc), "+v"(lmy));
-  fft_line<P, true, LI>(w, lb, lc, lmy, tws);
+  asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
+  fft_line<P, true, LI>(w, lb, lc, lds + loff, tws);
   apply_quad<E, false>(w, cj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), !cj, 1.0f);
   pair_stage<E, T, false>(x0, w, d + s_first * 3, d + 9 + s_first * 3, b, sgn, acc_ka, acc_kr);
 #pragma unroll
