@@ -410,11 +410,13 @@ __device__ __forceinline__ float block_sum(float x, float* red) {
 }
 
 // Partial written by every block; the last block to finish sums the partials
-// in block order (FP64) and stores the total, so the result does not depend
-// on completion order.  counter is reset for the next use.
+// in FP64 (thread t takes partials t, t + 256, ... in order, then a fixed
+// tree), so the result does not depend on completion order.  counter is
+// reset for the next use.
 __device__ __forceinline__ void finish_partials(float part, float* partials, unsigned* counter,
                                                 float* out, unsigned* status, int nblocks) {
   __shared__ int is_last;
+  __shared__ double sh[256];
   if (threadIdx.x == 0) {
     partials[blockIdx.x] = part;
     __threadfence();
@@ -422,16 +424,24 @@ __device__ __forceinline__ void finish_partials(float part, float* partials, uns
     is_last = (done == (unsigned)(nblocks - 1));
   }
   __syncthreads();
-  if (is_last) {
-    __threadfence();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int i = 0; i < nblocks; ++i) s += (double)partials[i];
-      float f = (float)s;
-      if (out) out[0] = f;
-      if (!isfinite(s)) atomicOr(status, 1u);
-      atomicExch(counter, 0u);
-    }
+  if (!is_last) return;
+  __threadfence();
+  // (slots are strided over the threads, so any block size works)
+  for (int t = threadIdx.x; t < 256; t += blockDim.x) {
+    double s = 0.0;
+    for (int i = t; i < nblocks; i += 256) s += (double)partials[i];
+    sh[t] = s;
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    for (int t = threadIdx.x; t < w; t += blockDim.x) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double s = sh[0];
+    if (out) out[0] = (float)s;
+    if (!isfinite(s)) atomicOr(status, 1u);
+    atomicExch(counter, 0u);
   }
 }
 

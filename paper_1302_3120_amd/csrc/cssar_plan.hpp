@@ -40,6 +40,9 @@ template <int N, int V> struct Plan;
 #ifndef CSSAR_LR4096
 #define CSSAR_LR4096 2
 #endif
+#ifndef CSSAR_C4096
+#define CSSAR_C4096 4
+#endif
 #define CSSAR_RT4096 (CSSAR_LR4096 * 4096 / CSSAR_E4096)
 
 //         N    V   E   C    RT   radices
@@ -56,7 +59,7 @@ CSSAR_PLAN(1536, 1, 24, 8, 256, 3, 8, 8, 8)
 CSSAR_PLAN(2048, 0, 16, 8, 256, 16, 16, 8)
 CSSAR_PLAN(2048, 1, 32, 8, 256, 16, 16, 8)
 CSSAR_PLAN(3072, 0, 24, 4, 512, 3, 8, 8, 8, 2)
-CSSAR_PLAN(4096, 0, CSSAR_E4096, 4, CSSAR_RT4096, 16, 16, 16)
+CSSAR_PLAN(4096, 0, CSSAR_E4096, CSSAR_C4096, CSSAR_RT4096, 16, 16, 16)
 CSSAR_PLAN(4096, 1, 32, 4, 256, 16, 16, 16)
 CSSAR_PLAN(8192, 0, 32, 2, 256, 16, 16, 16, 2)
 
