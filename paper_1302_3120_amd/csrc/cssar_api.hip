@@ -103,6 +103,19 @@ int occupancy(const void* fn, int block) {
   return n;
 }
 
+// Plan variant of the single-array column pass of each kind.  With
+// CSSAR_COL_V4096 = 1 the forward column passes at 4096 use the
+// split-exchange plan (two workgroups per CU); measured slower on MI355X
+// (update 103 vs 94 us, residual 112 vs 106 us), so variant 0 is the
+// default; the adjoint passes always keep variant 0.
+#ifndef CSSAR_COL_V4096
+#define CSSAR_COL_V4096 0
+#endif
+int column_variant(int n, int which) {
+  if (n == 4096 && which <= CK_R) return CSSAR_COL_V4096;
+  return 0;
+}
+
 int grid_for(int work, int cus, int per_cu) {
   int g = std::min(work, cus * per_cu);
   if (g >= 16) g -= g % 8;  // lets the kernels renumber blocks per XCD
@@ -173,7 +186,7 @@ int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s) {
 }
 
 int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
-  return timed(op, 2 + which, s, [&] { return op->ka->col[which](a, op->grid_col[which], s); });
+  return timed(op, 2 + which, s, [&] { return op->kcol[which]->col[which](a, op->grid_col[which], s); });
 }
 
 int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s) {
@@ -264,9 +277,11 @@ int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** ou
   op->grid_row = grid_for(row_work, op->cus, occupancy(kr->row_fn, kr->RT));
   for (int c = 0; c < 2; ++c)
     op->grid_adj[c] = std::min(grid_for(row_work, op->cus, occupancy(kr->row_adj_fn[c], kr->RT)), kMaxPartials / 2);
-  const int col_work = n_rg / ka->C;
   for (int w = 0; w < CK_COUNT; ++w) {
-    op->grid_col[w] = grid_for(col_work, op->cus, occupancy(ka->col_fn[w], ka->CT));
+    const KernelTable* kt = table_for(n_az, column_variant(n_az, w));
+    if (!kt || n_rg % kt->C != 0) kt = ka;
+    op->kcol[w] = kt;
+    op->grid_col[w] = grid_for(n_rg / kt->C, op->cus, occupancy(kt->col_fn[w], kt->CT));
     if (op->grid_col[w] > kMaxPartials) op->grid_col[w] = kMaxPartials;
   }
   *out = op;

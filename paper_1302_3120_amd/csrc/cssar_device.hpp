@@ -208,11 +208,33 @@ struct TwLds {  // two-level table in LDS: w^e = lo[e % 64] hi[e / 64]
   __device__ __forceinline__ float2 operator()(int e) const { return cmul(lo[e & 63], hi[e >> 6]); }
 };
 
+// Twiddle powers w^(j m step), m < 16, of one Stockham pass for the
+// butterfly index j of a thread.  With one butterfly per thread (E = R),
+// j = b mod L is the same for every line the thread transforms, so a
+// persistent kernel computes them once.
+struct TwPowers {
+  float2 w[16];
+};
+
+template <int N, int E, int R, int L, typename TW>
+__device__ __forceinline__ TwPowers tw_powers(int b, const TW& tws) {
+  constexpr int step = N / (L * R);
+  TwPowers h;
+  h.w[0] = make_float2(1.f, 0.f);
+  h.w[1] = tws((b % L) * step);
+#pragma unroll
+  for (int m = 2; m < R; ++m) {
+    const int hi = 1 << (31 - __builtin_clz(m));
+    h.w[m] = (m == hi) ? cmul(h.w[m / 2], h.w[m / 2]) : cmul(h.w[hi], h.w[m - hi]);
+  }
+  return h;
+}
+
 // Radix-R butterflies of one Stockham pass on the thread's registers.  The
 // twiddles w^(j m), m < R, come from one lookup of w^j and products of at
-// most four factors for the rest.
-template <int N, int E, int R, int L, bool INV, typename TW>
-__device__ __forceinline__ void stockham_compute(float2 (&v)[E], int b, const TW& tws) {
+// most four factors for the rest, or from precomputed powers (HP).
+template <int N, int E, int R, int L, bool INV, typename TW, bool HP = false>
+__device__ __forceinline__ void stockham_compute(float2 (&v)[E], int b, const TW& tws, const TwPowers& hp) {
   constexpr int Q = E / R;
   constexpr int T = N / E;
 #pragma unroll
@@ -220,7 +242,11 @@ __device__ __forceinline__ void stockham_compute(float2 (&v)[E], int b, const TW
     float2 a[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) a[m] = v[q + Q * m];
-    if constexpr (L > 1) {
+    if constexpr (HP) {
+      static_assert(Q == 1 && L > 1, "precomputed twiddles need one butterfly per thread");
+#pragma unroll
+      for (int m = 1; m < R; ++m) a[m] = INV ? cmulc(a[m], hp.w[m]) : cmul(a[m], hp.w[m]);
+    } else if constexpr (L > 1) {
       const int beta = b + T * q;
       const int j = beta % L;
       constexpr int step = N / (L * R);
@@ -291,20 +317,81 @@ __device__ __forceinline__ void stockham_exchange(float2 (&v)[E], int b, int c, 
   __syncthreads();
 }
 
+// The same exchange through half the LDS, in two rounds: with two
+// butterflies per thread (E = 2R) and T R = N/2, butterfly q of every thread
+// writes only into half q of the line, and the reads x[b + T k] of half q
+// are k in [q E/2, (q+1) E/2); round q writes butterfly q, then every
+// thread reads its half-q elements.  Lets two column workgroups share a
+// compute unit's LDS.
+template <int N, int E, int R, int L, int C>
+__device__ __forceinline__ void stockham_exchange_split(float2 (&v)[E], int b, int c, float2* lds) {
+  constexpr int Q = E / R;
+  constexpr int T = N / E;
+  constexpr int H = N / 2;
+  static_assert(Q == 2 && T * R == H && T % L == 0 && T % 16 == 0, "split exchange");
+  float2 t[E];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int beta = b + T * h;
+    const int j = beta % L;
+    const int base = (beta - j) * R + j - h * H;  // position in half h
+    if constexpr (L % 16 == 0 || (L == 1 && 16 % R == 0)) {
+      const unsigned off = lds_pad<C>((unsigned)(base * C + c));
+      __builtin_assume(off < 32768u);
+      float2* p = lds + off;
+      constexpr int step = L == 1 ? C : L * C + L * C / 16;
+#pragma unroll
+      for (int m = 0; m < R; ++m) p[m * step] = v[h + Q * m];
+    } else {
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[lds_pad<C>((base + L * m) * C + c)] = v[h + Q * m];
+    }
+    __syncthreads();
+    const unsigned off = lds_pad<C>((unsigned)(b * C + c));
+    __builtin_assume(off < 32768u);
+    const float2* p = lds + off;
+    constexpr int step = T * C + T * C / 16;
+#pragma unroll
+    for (int k = 0; k < E / 2; ++k) t[h * (E / 2) + k] = p[k * step];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < E; ++k) v[k] = t[k];
+}
+
 // One length-N transform (plan P) of the line held by the thread's
-// registers (x[b + T k] in v[k]), lines interleaved C-wide in LDS.
-template <class P, bool INV, int C, typename TW, int S = 0>
-__device__ __forceinline__ void fft_line(float2 (&v)[P::E], int b, int c, float2* lds, const TW& tws) {
+// registers (x[b + T k] in v[k]), lines interleaved C-wide in LDS (of N or,
+// with SPL, N/2 points per line).
+template <class P, bool INV, int C, typename TW, int S = 0, int HS = -1, bool SPL = false>
+__device__ __forceinline__ void fft_line(float2 (&v)[P::E], int b, int c, float2* lds, const TW& tws,
+                                         const TwPowers& hp) {
   constexpr int N = P::N;
   if constexpr (S < P::P) {
     constexpr int R = P::radix(S);
     constexpr int L = P::sub(S);
     __builtin_amdgcn_sched_barrier(0);
-    stockham_compute<N, P::E, R, L, INV>(v, b, tws);
+    stockham_compute<N, P::E, R, L, INV, TW, S == HS>(v, b, tws, hp);
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (S + 1 < P::P) stockham_exchange<N, P::E, R, L, C>(v, b, c, lds);
-    fft_line<P, INV, C, TW, S + 1>(v, b, c, lds, tws);
+    if constexpr (S + 1 < P::P) {
+      if constexpr (SPL) stockham_exchange_split<N, P::E, R, L, C>(v, b, c, lds);
+      else stockham_exchange<N, P::E, R, L, C>(v, b, c, lds);
+    }
+    fft_line<P, INV, C, TW, S + 1, HS, SPL>(v, b, c, lds, tws, hp);
   }
+}
+
+// Transform without precomputed twiddles.
+template <class P, bool INV, int C, typename TW, bool SPL = false>
+__device__ __forceinline__ void fft_line(float2 (&v)[P::E], int b, int c, float2* lds, const TW& tws) {
+  TwPowers none;
+  fft_line<P, INV, C, TW, 0, -1, SPL>(v, b, c, lds, tws, none);
+}
+
+// Pass whose twiddles a thread can precompute for every line (-1: none):
+// the second pass, when each thread holds exactly one butterfly of it.
+template <class P>
+constexpr int hoisted_pass() {
+  return (P::P >= 2 && P::radix(1) == P::E && P::radix(1) <= 16) ? 1 : -1;
 }
 
 // Fill a two-level twiddle table (64 + N/64 entries) from the global table.
@@ -356,6 +443,13 @@ __device__ __forceinline__ float2 cis_quad(const Quad& q, int k) {
   const float r = (float)((t4 - qn) * 0.25);
   return cis_quadrant(r, (int)qn);
 #endif
+}
+
+// exp(2 pi i t) for an FP64 argument in turns: FP64 reduction to
+// [-1/2, 1/2], then the hardware FP32 sine and cosine.
+__device__ __forceinline__ float2 cis_turns(double t) {
+  const float r = (float)(t - rint(t));
+  return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
 }
 
 // ------------------------------------------------------- buffer access --

@@ -44,6 +44,7 @@ struct cssar_op {
   int cus = 0;
   const cssar::KernelTable* ka = nullptr;  // azimuth length N_a (column passes)
   const cssar::KernelTable* kr = nullptr;  // range length N_r (row passes)
+  const cssar::KernelTable* kcol[cssar::CK_COUNT] = {};  // per column-pass kind (N_a)
   double2* rowc1 = nullptr;         // per Doppler bin: Phi1 (a1, d1)
   double2* rowc2 = nullptr;         //                  Phi2 (a2, b2)
   double2* rowc3 = nullptr;         //                  Phi3 (D, b3)

@@ -143,14 +143,49 @@ __device__ __forceinline__ Quad phi2_quad(double2 c, int b, int T) {
 
 // v[k] *= exp(+-2 pi i phase(k')) * s, with k' = k - E/2 (column offset
 // screens) or the signed bin slot (frequency screen: k' = k or k - E).
+//
+// CSSAR_PHASE_REC 1: the slot phases k' = 0, 1, ... and -1, -2, ... follow
+// from k' = 0 by products, z(k' +- 1) = z(k') r(k'), r(k' +- 1) = r(k') q,
+// with z(0) = exp(2 pi i A), r = exp(2 pi i (C +- B)), q = exp(4 pi i C)
+// each evaluated from its FP64 argument (four evaluations per thread and
+// line instead of one per element; the product error grows with |k'| <= E/2).
+// 0: every element's phase from its FP64 argument.
+#ifndef CSSAR_PHASE_REC
+#define CSSAR_PHASE_REC 0
+#endif
+
 template <int E, bool FREQ>
 __device__ __forceinline__ void apply_quad(float2 (&v)[E], const Quad& q, bool conj, float s) {
+#if CSSAR_PHASE_REC
+  // slot of k': column screens k' = k - E/2, frequency screen k' = k or k - E
+  auto slot = [](int kk) { return FREQ ? (kk >= 0 ? kk : kk + E) : kk + E / 2; };
+  auto cj = [&](float2 z) { return conj ? make_float2(z.x, -z.y) : z; };
+  const float2 z0 = cscale(cj(cis_turns(q.A)), s);
+  const float2 qq = cj(cis_turns(2.0 * q.C));
+  float2 z = z0, r = cj(cis_turns(q.B + q.C));
+#pragma unroll
+  for (int kk = 0; kk < E / 2; ++kk) {
+    v[slot(kk)] = cmul(v[slot(kk)], z);
+    if (kk + 1 < E / 2) z = cmul(z, r);
+    if (kk + 2 < E / 2) r = cmul(r, qq);
+  }
+  r = cj(cis_turns(q.C - q.B));
+  z = cmul(z0, r);
+  r = cmul(r, qq);
+#pragma unroll
+  for (int kk = -1; kk >= -E / 2; --kk) {
+    v[slot(kk)] = cmul(v[slot(kk)], z);
+    if (kk - 1 >= -E / 2) z = cmul(z, r);
+    if (kk - 2 >= -E / 2) r = cmul(r, qq);
+  }
+#else
   chunked<E, 4>([&](int k) {
     const int kk = FREQ ? (k < E / 2 ? k : k - E) : k - E / 2;
     float2 p = cis_quad(q, kk);
     p = make_float2(p.x * s, (conj ? -p.y : p.y) * s);
     v[k] = cmul(v[k], p);
   });
+#endif
 }
 
 __device__ __forceinline__ int xcd_logical_block() {
@@ -219,15 +254,17 @@ struct RowLds {
 // One unit (LR rows) of the row pass of array a:
 //   M: x Phi1 -> F_tau -> x Phi2 / N_r -> F_tau^-1 -> x Phi3
 //   G: x Phi3* -> F_tau -> x Phi2* / N_r -> F_tau^-1 -> x Phi1*
-template <class P>
+// CJ: 0 (M) or 1 (G) fixed at compile time, -1 read from a.conj.
+template <class P, int CJ = -1>
 __device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane<P>& ln, float2* lds,
-                                         const float2* twl) {
+                                         const float2* twl, const TwPowers& hp) {
+  constexpr int HS = hoisted_pass<P>();
   constexpr int N = P::N, E = P::E, T = P::T, LR = P::LR;
   constexpr int LI = RowLds<P>::LI, LS = RowLds<P>::LS;
   const uint32_t S = b4_stride(N);
   const uint32_t bytes = clamp_bytes(b4_bytes(a.na, N));
   const Buf in(a.in, bytes), out(a.out, bytes);
-  const bool conj = a.conj != 0;
+  const bool conj = CJ >= 0 ? CJ != 0 : a.conj != 0;
   const int b = ln.b, line = ln.line;
   const int row = gi * LR + line;
   const uint32_t vo = (uint32_t)(row >> 2) * S + (uint32_t)(b >> 2) * 128u + (uint32_t)(row & 3) * 32u +
@@ -245,26 +282,29 @@ __device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane
   const TwLds tws{twl, twl + 64};
   // first range-Doppler screen: Phi1 (M) or Phi3* (G)
   apply_quad<E, false>(v, conj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), conj, 1.0f);
-  fft_line<P, false, LI>(v, lb, lc, lds + loff, tws);
+  fft_line<P, false, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
   apply_quad<E, true>(v, phi2_quad(c2, b, T), conj, a.scale);
   asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
-  fft_line<P, true, LI>(v, lb, lc, lds + loff, tws);
+  fft_line<P, true, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
   // second range-Doppler screen: Phi3 (M) or Phi1* (G)
   apply_quad<E, false>(v, conj ? phi1_quad(c1, a, b, T) : phi3_quad(c3, a, b, T), conj, 1.0f);
 #pragma unroll
   for (int k = 0; k < E; ++k) out.st(v[k], vo, T * k * 32);
 }
 
-template <class P>
+template <class P, int CJ>
 __global__ __launch_bounds__(P::RT) void row_pass_kernel(RowArgs a) {
   __shared__ float2 lds[RowLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
   load_twiddle_table<P::N>(twl, a.tw);
   __syncthreads();
   const RowLane<P> ln;
+  TwPowers hp;
+  if constexpr (hoisted_pass<P>() >= 0)
+    hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(ln.b, TwLds{twl, twl + 64});
   const int units = a.na / P::LR;  // N_a is a multiple of LR
   for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x)
-    row_unit<P>(a, gi, ln, lds, twl);
+    row_unit<P, CJ>(a, gi, ln, lds, twl, hp);
 }
 
 template <class P>
@@ -275,9 +315,12 @@ __global__ __launch_bounds__(P::RT) void row_group_kernel(GroupArgs g) {
   load_twiddle_table<P::N>(twl, args[0].tw);  // w_N depends on N only
   __syncthreads();
   const RowLane<P> ln;
+  TwPowers hp;
+  if constexpr (hoisted_pass<P>() >= 0)
+    hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(ln.b, TwLds{twl, twl + 64});
   for (int u = xcd_logical_block(); u < g.total; u += gridDim.x) {
     const int s = group_find(g.start, g.count, u);
-    row_unit<P>(args[s], u - g.start[s], ln, lds, twl);
+    row_unit<P>(args[s], u - g.start[s], ln, lds, twl, hp);
   }
 }
 
@@ -393,9 +436,34 @@ __global__ __launch_bounds__(P::RT) void row_adj_kernel(RowArgs a) {
 // ---------------------------------------------------------- column pass --
 // One tile (C adjacent columns) of a column pass of array a.  Returns the
 // thread's share of the tile's squared norm (FWD with the mask, R).
+// Software pipelining of the update pass: Xt of the next tile is loaded
+// while this tile is transformed, into registers that are free at that
+// point, so one workgroup per compute unit keeps HBM busy during its FFTs.
+// (The residual pass has no free registers for it; split plans get the
+// overlap from a second workgroup instead.)
 template <class P, int MODE>
+constexpr bool col_pipelined() { return MODE == COL_A && !P::SPLIT; }
+
+template <class P, int MODE>
+__device__ __forceinline__ void col_preload(const ColArgs& a, int tile, int b, int c, float2 (&pre)[P::E]) {
+  constexpr int E = P::E, T = P::T, C = P::C;
+  const uint32_t b4b = clamp_bytes(b4_bytes(P::N, a.nr));
+  const Addr ab = col_addr(B4, b, tile * C + c, T, a.nr);
+  if constexpr (MODE == COL_A) {
+    if (a.flags & 1) return;  // first iteration: no Xt
+    const Buf in0(a.in0, b4b);
+#pragma unroll
+    for (int k = 0; k < E; ++k) pre[k] = in0.f2(ab.voff, k * ab.kstep);
+  } else if constexpr (MODE == COL_R) {
+    const Buf in0(a.in0, b4b);
+#pragma unroll
+    for (int k = 0; k < E; ++k) pre[k] = in0.f2(ab.voff, k * ab.kstep);
+  }
+}
+
+template <class P, int MODE, bool PIPE = false>
 __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int c, float2* lds,
-                                          const float2* twl) {
+                                          const float2* twl, float2 (&pre)[P::E], int next) {
   constexpr int N = P::N, E = P::E, T = P::T, C = P::C;
   const uint32_t rmb = clamp_bytes((size_t)N * a.nr * 8), b4b = clamp_bytes(b4_bytes(N, a.nr));
   constexpr int in_layout = MODE == COL_FWD ? RM : B4;
@@ -417,9 +485,12 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
     if (!first) {
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        const float2 x = in0.f2(ai.voff, k * ai.kstep);
+        const float2 x = PIPE ? pre[k] : in0.f2(ai.voff, k * ai.kstep);
         v[k] = make_float2(fmaf(a.scale, x.x, v[k].x), fmaf(a.scale, x.y, v[k].y));
       }
+    }
+    if constexpr (PIPE && MODE == COL_A) {
+      if (next >= 0) col_preload<P, MODE>(a, next, b, c, pre);
     }
     if constexpr (MODE == COL_VB) {
 #pragma unroll
@@ -430,8 +501,9 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
     for (int k = 0; k < E; ++k) v[k] = in0.f2(ai.voff, k * ai.kstep);
   } else {
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = cscale(in0.f2(ai.voff, k * ai.kstep), a.scale);
-    if constexpr (MODE == COL_R || MODE == COL_U) {
+    for (int k = 0; k < E; ++k) v[k] = cscale(PIPE ? pre[k] : in0.f2(ai.voff, k * ai.kstep), a.scale);
+    // (split plans load m o y after the inverse transform: registers)
+    if constexpr ((MODE == COL_R && !P::SPLIT) || MODE == COL_U) {
 #pragma unroll
       for (int k = 0; k < E; ++k) y2[k] = yb.f2(ab.voff, k * ab.kstep);
     }
@@ -460,11 +532,11 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
           out2.st(keep ? v[k] : make_float2(__uint_as_float(kUnsampled), 0.f), ab.voff, k * ab.kstep);
       }
     }
-    fft_line<P, false, C>(v, lb, lc, lds, tws);
+    fft_line<P, false, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
   } else if constexpr (MODE == COL_INV) {
-    fft_line<P, true, C>(v, lb, lc, lds, tws);
+    fft_line<P, true, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
   } else if constexpr (MODE == COL_A) {
-    fft_line<P, true, C>(v, lb, lc, lds, tws);
+    fft_line<P, true, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
     // X+ = S_sigma(V)
     const float s2 = a.sigma * a.sigma;
 #pragma unroll
@@ -475,14 +547,14 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
     }
     if (!(a.flags & 2)) {
       asm volatile("" : "+v"(lb), "+v"(lc));
-      fft_line<P, false, C>(v, lb, lc, lds, tws);  // Xt+ = F X+
+      fft_line<P, false, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);  // Xt+ = F X+
     }
   } else if constexpr (MODE == COL_VB) {
     // Vbar = J_S(V)^T Xbar (the threshold's real Jacobian, symmetric):
     // on |V| > sigma, (1 - sigma/|V|) Xbar + sigma Re(conj(V) Xbar) V / |V|^3;
     // d X+ / d sigma = -V/|V| gives the partial -Re(conj(V) Xbar)/|V|.
     // The support test is the update pass's, on the same V.
-    fft_line<P, true, C>(v, lb, lc, lds, tws);
+    fft_line<P, true, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
     const float s2 = a.sigma * a.sigma;
 #pragma unroll
     for (int k = 0; k < E; ++k) {
@@ -501,10 +573,10 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
       v[k] = cscale(vb, a.mu);
     }
     asm volatile("" : "+v"(lb), "+v"(lc));
-    fft_line<P, false, C>(v, lb, lc, lds, tws);  // F (mu Vbar)
+    fft_line<P, false, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);  // F (mu Vbar)
   } else if constexpr (MODE == COL_U) {
     // g = F^-1[F G mu Vbar] / N_a; ybar += m o g; ubar = -m o g; out = F ubar
-    fft_line<P, true, C>(v, lb, lc, lds, tws);
+    fft_line<P, true, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const bool keep = __float_as_uint(y2[k].x) != kUnsampled;
@@ -513,23 +585,37 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
       v[k] = make_float2(-g.x, -g.y);
     }
     asm volatile("" : "+v"(lb), "+v"(lc));
-    fft_line<P, false, C>(v, lb, lc, lds, tws);
+    fft_line<P, false, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
   } else if constexpr (MODE == COL_XB) {
     // Xbar = Vbar + F^-1[F M ubar] / N_a (spatial)
-    fft_line<P, true, C>(v, lb, lc, lds, tws);
+    fft_line<P, true, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = cadd(y3[k], v[k]);
   } else {  // COL_R: GX = F^-1[W] / N_a; R = m o y - m o GX; out = F R
-    fft_line<P, true, C>(v, lb, lc, lds, tws);
+    fft_line<P, true, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
+    // split plans: m o y in chunks of 8 after the transform (registers)
+    constexpr int YC = P::SPLIT ? 8 : E;
 #pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const bool keep = __float_as_uint(y2[k].x) != kUnsampled;
-      const float2 r = keep ? csub(y2[k], v[k]) : make_float2(0.f, 0.f);
-      acc = fmaf(r.x, r.x, fmaf(r.y, r.y, acc));
-      v[k] = r;
+    for (int k0 = 0; k0 < E; k0 += YC) {
+      if constexpr (P::SPLIT) {
+#pragma unroll
+        for (int k = k0; k < k0 + YC; ++k) y2[k] = yb.f2(ab.voff, k * ab.kstep);
+      }
+#pragma unroll
+      for (int k = k0; k < k0 + YC; ++k) {
+        const float2 yk = y2[k];
+        const bool keep = __float_as_uint(yk.x) != kUnsampled;
+        const float2 r = keep ? csub(yk, v[k]) : make_float2(0.f, 0.f);
+        acc = fmaf(r.x, r.x, fmaf(r.y, r.y, acc));
+        v[k] = r;
+      }
+      if constexpr (P::SPLIT) __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (PIPE) {
+      if (next >= 0) col_preload<P, MODE>(a, next, b, c, pre);
     }
     asm volatile("" : "+v"(lb), "+v"(lc));
-    fft_line<P, false, C>(v, lb, lc, lds, tws);
+    fft_line<P, false, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
   }
   const Addr ao = out_layout == RM ? col_addr(RM, b, j, T, a.nr) : ab;
 #pragma unroll
@@ -537,10 +623,18 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
   return acc;
 }
 
+// Column passes keep a whole tile in LDS (one workgroup per CU), or half of
+// it with the split exchange (two workgroups per CU: 4 waves per SIMD).
+template <class P>
+struct ColLds {
+  static constexpr int size = LdsSize<P::C, P::SPLIT ? P::N / 2 : P::N>::value;
+  static constexpr int waves_per_eu = P::SPLIT ? 2 * P::CT / 256 : 1;
+};
+
 template <class P, int MODE>
-__global__ __launch_bounds__(P::CT) void col_pass_kernel(ColArgs a) {
+__global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kernel(ColArgs a) {
   constexpr int C = P::C, CT = P::CT;
-  __shared__ float2 lds[LdsSize<C, P::N>::value];
+  __shared__ float2 lds[ColLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
   __shared__ float red[CT / 64];
   load_twiddle_table<P::N>(twl, a.tw);
@@ -548,9 +642,17 @@ __global__ __launch_bounds__(P::CT) void col_pass_kernel(ColArgs a) {
   const int c = threadIdx.x % C;
   const int b = threadIdx.x / C;
   const int ntiles = a.nr / C;  // N_r is a multiple of C
+  constexpr bool PIPE = col_pipelined<P, MODE>();
   float acc = 0.f;
-  for (int tile = xcd_logical_block(); tile < ntiles; tile += gridDim.x)
-    acc += col_unit<P, MODE>(a, tile, b, c, lds, twl);
+  float2 pre[P::E];
+  int tile = xcd_logical_block();
+  if constexpr (PIPE) {
+    if (tile < ntiles) col_preload<P, MODE>(a, tile, b, c, pre);
+  }
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int next = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : -1;
+    acc += col_unit<P, MODE, PIPE>(a, tile, b, c, lds, twl, pre, next);
+  }
   const bool want_norm = (MODE == COL_R) || (MODE == COL_FWD && (a.flags & 1));
   if (want_norm) {
     const float part = block_sum<CT>(acc, red);
@@ -564,18 +666,19 @@ __global__ __launch_bounds__(P::CT) void col_pass_kernel(ColArgs a) {
 
 // Grouped column pass (batched solver): no norms are formed.
 template <class P, int MODE>
-__global__ __launch_bounds__(P::CT) void col_group_kernel(GroupArgs g) {
+__global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_group_kernel(GroupArgs g) {
   constexpr int C = P::C;
-  __shared__ float2 lds[LdsSize<C, P::N>::value];
+  __shared__ float2 lds[ColLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
   const ColArgs* __restrict__ args = (const ColArgs*)g.args;
   load_twiddle_table<P::N>(twl, args[0].tw);
   __syncthreads();
   const int c = threadIdx.x % C;
   const int b = threadIdx.x / C;
+  float2 pre[P::E];
   for (int u = xcd_logical_block(); u < g.total; u += gridDim.x) {
     const int s = group_find(g.start, g.count, u);
-    (void)col_unit<P, MODE>(args[s], u - g.start[s], b, c, lds, twl);
+    (void)col_unit<P, MODE>(args[s], u - g.start[s], b, c, lds, twl, pre, -1);
   }
 }
 
@@ -583,7 +686,10 @@ __global__ __launch_bounds__(P::CT) void col_group_kernel(GroupArgs g) {
 template <class P>
 struct Kernels {
   static hipError_t row(const RowArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(row_pass_kernel<P>, dim3(grid), dim3(P::RT), 0, s, a);
+    if (a.conj)
+      hipLaunchKernelGGL((row_pass_kernel<P, 1>), dim3(grid), dim3(P::RT), 0, s, a);
+    else
+      hipLaunchKernelGGL((row_pass_kernel<P, 0>), dim3(grid), dim3(P::RT), 0, s, a);
     return hipGetLastError();
   }
   template <int MODE>

@@ -17,7 +17,7 @@ template <int N, int V> struct Plan;
 // blocks of the blocked layout; with LR = 2 two workgroups share each block
 // (64 bytes each), which halves the LDS per workgroup so that two fit on a
 // compute unit; LR = 1 is the fallback for the longest lines.
-#define CSSAR_PLAN(NN, VV, EE, CC, RTT, ...)                                          \
+#define CSSAR_PLAN_S(NN, VV, EE, CC, RTT, SPL, ...)                                          \
   template <> struct Plan<NN, VV> {                                                   \
     static constexpr int N = NN;                                                      \
     static constexpr int V = VV;                                                      \
@@ -32,7 +32,10 @@ template <int N, int V> struct Plan;
     static constexpr int RT = RTT;    /* row-pass workgroup threads */                \
     static constexpr int LR = RT / T; /* rows per row-pass workgroup */               \
     static constexpr int CT = C * T;  /* column-pass workgroup threads */             \
+    /* column passes exchange through half the LDS (two workgroups per CU) */         \
+    static constexpr bool SPLIT = SPL;                                                \
   };
+#define CSSAR_PLAN(NN, VV, EE, CC, RTT, ...) CSSAR_PLAN_S(NN, VV, EE, CC, RTT, false, __VA_ARGS__)
 
 #ifndef CSSAR_E4096
 #define CSSAR_E4096 16
@@ -60,10 +63,11 @@ CSSAR_PLAN(2048, 0, 16, 8, 256, 16, 16, 8)
 CSSAR_PLAN(2048, 1, 32, 8, 256, 16, 16, 8)
 CSSAR_PLAN(3072, 0, 24, 4, 512, 3, 8, 8, 8, 2)
 CSSAR_PLAN(4096, 0, CSSAR_E4096, CSSAR_C4096, CSSAR_RT4096, 16, 16, 16)
-CSSAR_PLAN(4096, 1, 32, 4, 256, 16, 16, 16)
+CSSAR_PLAN_S(4096, 1, 32, 4, 256, true, 16, 16, 16)
 CSSAR_PLAN(8192, 0, 32, 2, 256, 16, 16, 16, 2)
 
 #undef CSSAR_PLAN
+#undef CSSAR_PLAN_S
 
 // Sanity checks evaluated at compile time for every plan.
 template <class P>

@@ -28,7 +28,7 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
       {&K::template col_group<COL_FWD>, &K::template col_group<COL_INV>,
        &K::template col_group<COL_A>, &K::template col_group<COL_R>},
       {&K::template row_adj<0>, &K::template row_adj<1>},
-      reinterpret_cast<const void*>(&row_pass_kernel<P>),
+      reinterpret_cast<const void*>(&row_pass_kernel<P, 0>),
       {reinterpret_cast<const void*>(&col_pass_kernel<P, COL_FWD>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_INV>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_A>),
