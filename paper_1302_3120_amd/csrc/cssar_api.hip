@@ -132,6 +132,11 @@ ColArgs col_args(const cssar_op* op) {
   a.partials = op->partials;
   a.counter = op->counter;
   a.status = op->counter + 1;
+  a.rowc1 = op->rowc1;
+  a.rowc3 = op->rowc3;
+  a.inv_fs = 1.0 / op->p.fs;
+  a.fc_fs = op->p.fc / op->p.fs;
+  a.p_c = op->p.fc * 2.0 * op->p.r_ref / kC;
   return a;
 }
 
@@ -187,6 +192,15 @@ int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s) {
 
 int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
   return timed(op, 2 + which, s, [&] { return op->kcol[which]->col[which](a, op->grid_col[which], s); });
+}
+
+int launch_row_mid(cssar_op* op, const RowArgs& a, hipStream_t s) {
+  return timed(op, a.conj ? 1 : 0, s, [&] { return op->kr->row_mid(a, op->grid_row, s); });
+}
+
+int launch_col_scr(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
+  const KernelTable* kt = op->kcol[which];
+  return timed(op, 2 + which, s, [&] { return kt->col_scr[which](a, op->grid_col[which], s); });
 }
 
 int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s) {
@@ -347,6 +361,23 @@ int cssar_apply_G(cssar_op* op, const void* x, void* y_out, void* ws, void* stre
   return launch_col(op, CK_INV, a, s);
 }
 
+// The solver's iteration with the range-Doppler screens moved into the
+// column passes (the row passes keep only the 2-D frequency screen).  The
+// state is Xh = Phi3* o F_eta X (Phi3 applied on the update pass's input
+// and its conjugate on its output), so per iteration:
+//   row (Phi2*):      P = F_tau^-1 Phi2* F_tau Xh      = Phi1 o F_eta G X
+//   column residual:  Phi1* P -> residual -> F_eta R  -> Phi1 o F_eta R
+//   row (Phi2):       P = F_tau^-1 Phi2 F_tau P        = Phi3* o F_eta M R
+//   column update:    Phi3 (Xh + mu P) = F_eta X + mu F_eta M R -> threshold
+//                     -> Phi3* F_eta X+ (or X+ in the last iteration).
+// CSSAR_SCREENED 1 runs this screened schedule; 0 (default) keeps all
+// screens in the row passes.  Measured at 4096 on MI355X: screened rows
+// 60.5 us (unscreened 72) but screened update / residual passes 114 / 120 us
+// (97 / 108): the column passes slow down with their added work, so the
+// unscreened schedule is faster overall (345 vs 351 us per iteration).
+#ifndef CSSAR_SCREENED
+#define CSSAR_SCREENED 0
+#endif
 int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters,
                     void* x_out, float* resid_hist, void* ws, void* stream) {
   int rc = check_op(op);
@@ -357,9 +388,14 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
   if (x_out == y || x_out == ws || ws == y) return fail(CSSAR_EINVAL, "x_out, y and ws must not alias");
   hipStream_t s = (hipStream_t)stream;
   const size_t blk = align256(b4_bytes(op->na, op->nr));
-  float2* X = (float2*)ws;                       // Xt = F_eta X (blocked layout)
-  float2* P = (float2*)((char*)ws + blk);        // F_eta G X, F_eta R, F_eta M R (in place)
-  float2* Y = (float2*)((char*)ws + 2 * blk);    // m o y (blocked layout)
+  float2* X = (float2*)ws;                       // Xt = F_eta X (or Xh) (blocked layout)
+  float2* P = (float2*)((char*)ws + blk);        // pass buffer (in place)
+  float2* Y = (float2*)((char*)ws + 2 * blk);    // m o y (blocked layout, unsampled marked)
+  constexpr bool scr = CSSAR_SCREENED != 0;
+  auto col = [&](int which, const ColArgs& a) {
+    return (scr && which != CK_INV) ? launch_col_scr(op, which, a, s) : launch_col(op, which, a, s);
+  };
+  auto row = [&](const RowArgs& a) { return scr ? launch_row_mid(op, a, s) : launch_row(op, a, s); };
   ColArgs a = col_args(op);
   a.y = Y;
   a.mask = (const uint32_t*)mask_bits;
@@ -374,24 +410,24 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
       f.out = P;
       f.out2 = Y;
       f.flags = 1 | 4;
-      if ((rc = launch_col(op, CK_FWD, f, s))) return rc;
+      if ((rc = col(CK_FWD, f))) return rc;
     } else {
       // P = F_eta G X (row chain of G on Xt); then R = m o y - m o G X, P = F_eta R
-      if ((rc = launch_row(op, row_args(op, X, P, 1), s))) return rc;
+      if ((rc = row(row_args(op, X, P, 1)))) return rc;
       ColArgs r = a;
       r.in0 = P;
       r.out = P;
-      if ((rc = launch_col(op, CK_R, r, s))) return rc;
+      if ((rc = col(CK_R, r))) return rc;
     }
     // P = F_eta M R (row chain of M)
-    if ((rc = launch_row(op, row_args(op, P, P, 0), s))) return rc;
+    if ((rc = row(row_args(op, P, P, 0)))) return rc;
     ColArgs u = a;
     u.in0 = X;
     u.in1 = P;
     u.out = last ? (float2*)x_out : X;
     u.flags = (t == 0 ? 1 : 0) | (last ? 2 : 0);
     u.hist_out = nullptr;
-    if ((rc = launch_col(op, CK_A, u, s))) return rc;
+    if ((rc = col(CK_A, u))) return rc;
   }
   return CSSAR_OK;
 }

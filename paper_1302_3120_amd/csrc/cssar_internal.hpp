@@ -77,6 +77,8 @@ int check_op(const cssar_op* op);
 int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s);
 int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s);
 int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s);
+int launch_row_mid(cssar_op* op, const RowArgs& a, hipStream_t s);
+int launch_col_scr(cssar_op* op, int which, const ColArgs& a, hipStream_t s);
 
 // Per Doppler bin, the derivatives of the three phase arguments (radians)
 // with respect to K_a and K_r as polynomials of the centred column offset

@@ -108,6 +108,10 @@ struct ColArgs {
   unsigned* counter;     // last-block detection
   float* hist_out;       // where the total ||R||^2 goes (may be NULL)
   unsigned* status;      // bit 0: non-finite residual
+  // screened column passes (range-Doppler screens moved out of the row passes)
+  const double2* rowc1;  // per Doppler bin: Phi1 (a1, d1)
+  const double2* rowc3;  //                  Phi3 (D, b3)
+  double inv_fs, fc_fs, p_c;
 };
 
 // Elementwise work on the E register elements in chunks of CH, with
@@ -254,8 +258,10 @@ struct RowLds {
 // One unit (LR rows) of the row pass of array a:
 //   M: x Phi1 -> F_tau -> x Phi2 / N_r -> F_tau^-1 -> x Phi3
 //   G: x Phi3* -> F_tau -> x Phi2* / N_r -> F_tau^-1 -> x Phi1*
-// CJ: 0 (M) or 1 (G) fixed at compile time, -1 read from a.conj.
-template <class P, int CJ = -1>
+// CJ: 0 (M) or 1 (G) fixed at compile time, -1 read from a.conj.  MID:
+// only the 2-D frequency screen (the screened column passes apply the
+// range-Doppler ones).
+template <class P, int CJ = -1, bool MID = false>
 __device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane<P>& ln, float2* lds,
                                          const float2* twl, const TwPowers& hp) {
   constexpr int HS = hoisted_pass<P>();
@@ -281,18 +287,18 @@ __device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane
   asm volatile("" : "+v"(loff));
   const TwLds tws{twl, twl + 64};
   // first range-Doppler screen: Phi1 (M) or Phi3* (G)
-  apply_quad<E, false>(v, conj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), conj, 1.0f);
+  if constexpr (!MID) apply_quad<E, false>(v, conj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), conj, 1.0f);
   fft_line<P, false, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
   apply_quad<E, true>(v, phi2_quad(c2, b, T), conj, a.scale);
   asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
   fft_line<P, true, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
   // second range-Doppler screen: Phi3 (M) or Phi1* (G)
-  apply_quad<E, false>(v, conj ? phi1_quad(c1, a, b, T) : phi3_quad(c3, a, b, T), conj, 1.0f);
+  if constexpr (!MID) apply_quad<E, false>(v, conj ? phi1_quad(c1, a, b, T) : phi3_quad(c3, a, b, T), conj, 1.0f);
 #pragma unroll
   for (int k = 0; k < E; ++k) out.st(v[k], vo, T * k * 32);
 }
 
-template <class P, int CJ>
+template <class P, int CJ, bool MID>
 __global__ __launch_bounds__(P::RT) void row_pass_kernel(RowArgs a) {
   __shared__ float2 lds[RowLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
@@ -304,7 +310,7 @@ __global__ __launch_bounds__(P::RT) void row_pass_kernel(RowArgs a) {
     hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(ln.b, TwLds{twl, twl + 64});
   const int units = a.na / P::LR;  // N_a is a multiple of LR
   for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x)
-    row_unit<P, CJ>(a, gi, ln, lds, twl, hp);
+    row_unit<P, CJ, MID>(a, gi, ln, lds, twl, hp);
 }
 
 template <class P>
@@ -461,9 +467,41 @@ __device__ __forceinline__ void col_preload(const ColArgs& a, int tile, int b, i
   }
 }
 
-template <class P, int MODE, bool PIPE = false>
+// A range-Doppler screen on a column: element (Doppler bin i = b + T k,
+// range column j), from bin i's FP64 coefficients and the column offset
+// o = j - N_r/2 (tau' = o / fs), in turns:
+//   Phi1 = a1 (tau' - d1)^2,  Phi3 = D (p_c + o fc/fs) + b3 tau'^2.
+template <class P, int WHICH, bool CONJ>
+__device__ __forceinline__ void col_screen(float2 (&v)[P::E], const ColArgs& a, int b, int j) {
+  constexpr int E = P::E, T = P::T;
+  const double o = (double)(j - a.nr / 2);
+  const double tau = o * a.inv_fs;
+  const double pj = fma(o, a.fc_fs, a.p_c), tq = tau * tau;
+  const double2* __restrict__ rc = WHICH == 1 ? a.rowc1 : a.rowc3;
+  chunked<E, 4>([&](int k) {
+    const double2 cc = rc[b + T * k];
+    double t;
+    if constexpr (WHICH == 1) {
+      const double u = tau - cc.y;
+      t = cc.x * u * u;
+    } else {
+      t = fma(cc.x, pj, cc.y * tq);
+    }
+    const float2 p = cis_turns(t);
+    v[k] = CONJ ? cmulc(v[k], p) : cmul(v[k], p);
+  });
+}
+
+// SCR (screened passes of the solver): the residual pass applies Phi1* on
+// input and Phi1 on output, the update pass Phi3 on input and Phi3* on its
+// azimuth-spectrum output, the first forward pass Phi1 on output; the row
+// passes between them then carry only the 2-D frequency screen Phi2.
+// HT: the second pass's twiddles come precomputed (hp), per thread.
+template <class P, int MODE, bool PIPE = false, bool SCR = false, bool HT = false>
 __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int c, float2* lds,
-                                          const float2* twl, float2 (&pre)[P::E], int next) {
+                                          const float2* twl, float2 (&pre)[P::E], int next,
+                                          const TwPowers& hp) {
+  constexpr int HSC = HT ? hoisted_pass<P>() : -1;
   constexpr int N = P::N, E = P::E, T = P::T, C = P::C;
   const uint32_t rmb = clamp_bytes((size_t)N * a.nr * 8), b4b = clamp_bytes(b4_bytes(N, a.nr));
   constexpr int in_layout = MODE == COL_FWD ? RM : B4;
@@ -502,8 +540,9 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
   } else {
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = cscale(PIPE ? pre[k] : in0.f2(ai.voff, k * ai.kstep), a.scale);
-    // (split plans load m o y after the inverse transform: registers)
-    if constexpr ((MODE == COL_R && !P::SPLIT) || MODE == COL_U) {
+    // (split plans and screened passes load m o y after the inverse
+    // transform: registers)
+    if constexpr ((MODE == COL_R && !P::SPLIT && !SCR && !HT) || MODE == COL_U) {
 #pragma unroll
       for (int k = 0; k < E; ++k) y2[k] = yb.f2(ab.voff, k * ab.kstep);
     }
@@ -512,6 +551,8 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
       for (int k = 0; k < E; ++k) y3[k] = in1.f2(ab.voff, k * ab.kstep);
     }
   }
+  if constexpr (SCR && MODE == COL_R) col_screen<P, 1, true>(v, a, b, j);
+  if constexpr (SCR && MODE == COL_A) col_screen<P, 3, false>(v, a, b, j);
   const TwLds tws{twl, twl + 64};
   int lb = b, lc = c;
   asm volatile("" : "+v"(lb), "+v"(lc));  // recompute LDS addresses per tile
@@ -532,11 +573,11 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
           out2.st(keep ? v[k] : make_float2(__uint_as_float(kUnsampled), 0.f), ab.voff, k * ab.kstep);
       }
     }
-    fft_line<P, false, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
+    fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
   } else if constexpr (MODE == COL_INV) {
-    fft_line<P, true, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
+    fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
   } else if constexpr (MODE == COL_A) {
-    fft_line<P, true, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
+    fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
     // X+ = S_sigma(V)
     const float s2 = a.sigma * a.sigma;
 #pragma unroll
@@ -547,14 +588,14 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
     }
     if (!(a.flags & 2)) {
       asm volatile("" : "+v"(lb), "+v"(lc));
-      fft_line<P, false, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);  // Xt+ = F X+
+      fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);  // Xt+ = F X+
     }
   } else if constexpr (MODE == COL_VB) {
     // Vbar = J_S(V)^T Xbar (the threshold's real Jacobian, symmetric):
     // on |V| > sigma, (1 - sigma/|V|) Xbar + sigma Re(conj(V) Xbar) V / |V|^3;
     // d X+ / d sigma = -V/|V| gives the partial -Re(conj(V) Xbar)/|V|.
     // The support test is the update pass's, on the same V.
-    fft_line<P, true, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
+    fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
     const float s2 = a.sigma * a.sigma;
 #pragma unroll
     for (int k = 0; k < E; ++k) {
@@ -573,10 +614,10 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
       v[k] = cscale(vb, a.mu);
     }
     asm volatile("" : "+v"(lb), "+v"(lc));
-    fft_line<P, false, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);  // F (mu Vbar)
+    fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);  // F (mu Vbar)
   } else if constexpr (MODE == COL_U) {
     // g = F^-1[F G mu Vbar] / N_a; ybar += m o g; ubar = -m o g; out = F ubar
-    fft_line<P, true, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
+    fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const bool keep = __float_as_uint(y2[k].x) != kUnsampled;
@@ -585,19 +626,20 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
       v[k] = make_float2(-g.x, -g.y);
     }
     asm volatile("" : "+v"(lb), "+v"(lc));
-    fft_line<P, false, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
+    fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
   } else if constexpr (MODE == COL_XB) {
     // Xbar = Vbar + F^-1[F M ubar] / N_a (spatial)
-    fft_line<P, true, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
+    fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = cadd(y3[k], v[k]);
   } else {  // COL_R: GX = F^-1[W] / N_a; R = m o y - m o GX; out = F R
-    fft_line<P, true, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
-    // split plans: m o y in chunks of 8 after the transform (registers)
-    constexpr int YC = P::SPLIT ? 8 : E;
+    fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
+    // split plans, screened passes: m o y in chunks of 8 after the transform
+    constexpr bool late = P::SPLIT || SCR || HT;
+    constexpr int YC = late ? 8 : E;
 #pragma unroll
     for (int k0 = 0; k0 < E; k0 += YC) {
-      if constexpr (P::SPLIT) {
+      if constexpr (late) {
 #pragma unroll
         for (int k = k0; k < k0 + YC; ++k) y2[k] = yb.f2(ab.voff, k * ab.kstep);
       }
@@ -609,13 +651,17 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
         acc = fmaf(r.x, r.x, fmaf(r.y, r.y, acc));
         v[k] = r;
       }
-      if constexpr (P::SPLIT) __builtin_amdgcn_sched_barrier(0);
+      if constexpr (late) __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (PIPE) {
       if (next >= 0) col_preload<P, MODE>(a, next, b, c, pre);
     }
     asm volatile("" : "+v"(lb), "+v"(lc));
-    fft_line<P, false, C, TwLds, P::SPLIT>(v, lb, lc, lds, tws);
+    fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
+  }
+  if constexpr (SCR && (MODE == COL_FWD || MODE == COL_R)) col_screen<P, 1, false>(v, a, b, j);
+  if constexpr (SCR && MODE == COL_A) {
+    if (!(a.flags & 2)) col_screen<P, 3, true>(v, a, b, j);
   }
   const Addr ao = out_layout == RM ? col_addr(RM, b, j, T, a.nr) : ab;
 #pragma unroll
@@ -631,7 +677,7 @@ struct ColLds {
   static constexpr int waves_per_eu = P::SPLIT ? 2 * P::CT / 256 : 1;
 };
 
-template <class P, int MODE>
+template <class P, int MODE, bool SCR>
 __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kernel(ColArgs a) {
   constexpr int C = P::C, CT = P::CT;
   __shared__ float2 lds[ColLds<P>::size];
@@ -642,7 +688,12 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   const int c = threadIdx.x % C;
   const int b = threadIdx.x / C;
   const int ntiles = a.nr / C;  // N_r is a multiple of C
-  constexpr bool PIPE = col_pipelined<P, MODE>();
+  // the update and residual passes take the second pass's twiddles from
+  // registers (computed once here) instead of the prefetch
+  constexpr bool HT = (MODE == COL_A || MODE == COL_R) && hoisted_pass<P>() >= 0 && !P::SPLIT;
+  constexpr bool PIPE = col_pipelined<P, MODE>() && !SCR && !HT;
+  TwPowers hp;
+  if constexpr (HT) hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(b, TwLds{twl, twl + 64});
   float acc = 0.f;
   float2 pre[P::E];
   int tile = xcd_logical_block();
@@ -651,7 +702,7 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   }
   for (; tile < ntiles; tile += gridDim.x) {
     const int next = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : -1;
-    acc += col_unit<P, MODE, PIPE>(a, tile, b, c, lds, twl, pre, next);
+    acc += col_unit<P, MODE, PIPE, SCR, HT>(a, tile, b, c, lds, twl, pre, next, hp);
   }
   const bool want_norm = (MODE == COL_R) || (MODE == COL_FWD && (a.flags & 1));
   if (want_norm) {
@@ -678,23 +729,31 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_group_kern
   float2 pre[P::E];
   for (int u = xcd_logical_block(); u < g.total; u += gridDim.x) {
     const int s = group_find(g.start, g.count, u);
-    (void)col_unit<P, MODE>(args[s], u - g.start[s], b, c, lds, twl, pre, -1);
+    (void)col_unit<P, MODE>(args[s], u - g.start[s], b, c, lds, twl, pre, -1, TwPowers{});
   }
 }
 
 // Host-side launch helpers (one set per plan, instantiated in kern_inst.hip).
 template <class P>
 struct Kernels {
-  static hipError_t row(const RowArgs& a, int grid, hipStream_t s) {
+  template <bool MID>
+  static hipError_t row_t(const RowArgs& a, int grid, hipStream_t s) {
     if (a.conj)
-      hipLaunchKernelGGL((row_pass_kernel<P, 1>), dim3(grid), dim3(P::RT), 0, s, a);
+      hipLaunchKernelGGL((row_pass_kernel<P, 1, MID>), dim3(grid), dim3(P::RT), 0, s, a);
     else
-      hipLaunchKernelGGL((row_pass_kernel<P, 0>), dim3(grid), dim3(P::RT), 0, s, a);
+      hipLaunchKernelGGL((row_pass_kernel<P, 0, MID>), dim3(grid), dim3(P::RT), 0, s, a);
+    return hipGetLastError();
+  }
+  static hipError_t row(const RowArgs& a, int grid, hipStream_t s) { return row_t<false>(a, grid, s); }
+  static hipError_t row_mid(const RowArgs& a, int grid, hipStream_t s) { return row_t<true>(a, grid, s); }
+  template <int MODE>
+  static hipError_t col(const ColArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((col_pass_kernel<P, MODE, false>), dim3(grid), dim3(P::CT), 0, s, a);
     return hipGetLastError();
   }
   template <int MODE>
-  static hipError_t col(const ColArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((col_pass_kernel<P, MODE>), dim3(grid), dim3(P::CT), 0, s, a);
+  static hipError_t col_scr(const ColArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((col_pass_kernel<P, MODE, true>), dim3(grid), dim3(P::CT), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t row_group(const GroupArgs& g, int grid, hipStream_t s) {

@@ -28,14 +28,17 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
       {&K::template col_group<COL_FWD>, &K::template col_group<COL_INV>,
        &K::template col_group<COL_A>, &K::template col_group<COL_R>},
       {&K::template row_adj<0>, &K::template row_adj<1>},
-      reinterpret_cast<const void*>(&row_pass_kernel<P, 0>),
-      {reinterpret_cast<const void*>(&col_pass_kernel<P, COL_FWD>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_INV>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_A>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_R>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_VB>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_U>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_XB>)},
+      &K::row_mid,
+      {&K::template col_scr<COL_FWD>, &K::template col<COL_INV>, &K::template col_scr<COL_A>,
+       &K::template col_scr<COL_R>},
+      reinterpret_cast<const void*>(&row_pass_kernel<P, 0, false>),
+      {reinterpret_cast<const void*>(&col_pass_kernel<P, COL_FWD, false>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_INV, false>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_A, false>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_R, false>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_VB, false>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_U, false>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_XB, false>)},
       reinterpret_cast<const void*>(&row_group_kernel<P>),
       {reinterpret_cast<const void*>(&col_group_kernel<P, COL_FWD>),
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_INV>),
@@ -43,6 +46,11 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_R>)},
       {reinterpret_cast<const void*>(&row_adj_kernel<P, 0>),
        reinterpret_cast<const void*>(&row_adj_kernel<P, 1>)},
+      reinterpret_cast<const void*>(&row_pass_kernel<P, 0, true>),
+      {reinterpret_cast<const void*>(&col_pass_kernel<P, COL_FWD, true>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_INV, false>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_A, true>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_R, true>)},
   };
   return &t;
 }
