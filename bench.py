@@ -36,9 +36,12 @@ PASS_BYTES = {
 ITER_BYTES = 80.125
 # Kernel symbol of each pass kind (row_M and row_G share one kernel).
 KIND_SYMBOL = {
-    "row_M": "row_pass_kernel<{n}>", "row_G": "row_pass_kernel<{n}>",
-    "col_fwd": "col_pass_kernel<{n}, 0>", "col_inv": "col_pass_kernel<{n}, 1>",
-    "col_update_threshold": "col_pass_kernel<{n}, 2>", "col_residual": "col_pass_kernel<{n}, 3>",
+    "row_M": "row_pass_kernel<cssar::Plan<{n}, 0>, 0, false>",
+    "row_G": "row_pass_kernel<cssar::Plan<{n}, 0>, 1, false>",
+    "col_fwd": "col_pass_kernel<cssar::Plan<{n}, 0>, 0, false>",
+    "col_inv": "col_pass_kernel<cssar::Plan<{n}, 0>, 1, false>",
+    "col_update_threshold": "col_pass_kernel<cssar::Plan<{n}, 0>, 2, false>",
+    "col_residual": "col_pass_kernel<cssar::Plan<{n}, 0>, 3, false>",
 }
 # Counter-based HBM bytes per dispatch, written by --rocprof-summary from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and a copy-kernel calibration.
@@ -315,12 +318,13 @@ def rocprof_summary(stats_dir, fetch_dir, write_dir, n, command):
         _, w_kib = write_groups[wk[0]]
         fb = f_kib * 1024 * per["FETCH_SIZE"][0]
         wb = w_kib * 1024 * per["WRITE_SIZE"][0]
-        if kind != "row_G":
+        if True:
             lines.append("| %s | %d | %.1f | %.1f | %.1f | %.1f |" % (
                 fk[0], cnt, f_kib, w_kib, fb / 1e6, wb / 1e6))
         machine.append("traffic %s %.0f %.0f" % (kind, fb, wb))
     lines += ["", "Algorithmic bytes per dispatch: 16 B/pixel (row passes), 24 B/pixel (update and "
-                  "residual column passes; + 1/8 B/pixel mask for the residual pass).", "",
+                  "residual column passes), 24.125 B/pixel (first column pass: y, mask, two "
+                  "outputs).", "",
               "Machine-readable lines (kind, fetch bytes, write bytes per dispatch, scaled):", ""]
     lines += ["    " + m for m in machine]
     lines += ["    kernel_sources_sha256 " + kernel_source_digest(), ""]

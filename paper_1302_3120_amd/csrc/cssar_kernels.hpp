@@ -727,9 +727,13 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_group_kern
   const int c = threadIdx.x % C;
   const int b = threadIdx.x / C;
   float2 pre[P::E];
+  // same per-line arithmetic as the single-array kernel (bit-identical results)
+  constexpr bool HT = (MODE == COL_A || MODE == COL_R) && hoisted_pass<P>() >= 0 && !P::SPLIT;
+  TwPowers hp;
+  if constexpr (HT) hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(b, TwLds{twl, twl + 64});
   for (int u = xcd_logical_block(); u < g.total; u += gridDim.x) {
     const int s = group_find(g.start, g.count, u);
-    (void)col_unit<P, MODE>(args[s], u - g.start[s], b, c, lds, twl, pre, -1, TwPowers{});
+    (void)col_unit<P, MODE, false, false, HT>(args[s], u - g.start[s], b, c, lds, twl, pre, -1, hp);
   }
 }
 
