@@ -31,6 +31,8 @@
 // channels (without it a column walks a power-of-two stride).
 #pragma once
 
+#include <type_traits>
+
 #include "cssar_device.hpp"
 
 namespace cssar {
@@ -192,6 +194,34 @@ __device__ __forceinline__ void apply_quad(float2 (&v)[E], const Quad& q, bool c
 #endif
 }
 
+// The same screen from a per-line table: the slot phase A + B k' + C k'^2
+// (A, B per thread, C per line) is applied as exp(2 pi i A) exp(2 pi i B)^k'
+// tab[|k'|], with tab[m] = exp(2 pi i C m^2) computed once per line and
+// shared through LDS, and the powers of exp(2 pi i B) by products from
+// k' = 0 (at most E/2 of them).  Two evaluations per thread and screen
+// instead of one per element.
+template <int E, bool FREQ>
+__device__ __forceinline__ void apply_quad_tab(float2 (&v)[E], const Quad& q, const float2* tab, bool conj,
+                                               float s) {
+  auto slot = [](int kk) { return FREQ ? (kk >= 0 ? kk : kk + E) : kk + E / 2; };
+  auto cj = [&](float2 z) { return conj ? make_float2(z.x, -z.y) : z; };
+  const float2 z0 = cscale(cj(cis_turns(q.A)), s);
+  const float2 u = cj(cis_turns(q.B));
+  const float2 ub = make_float2(u.x, -u.y);  // u^-1 (|u| = 1)
+  float2 w = z0;
+#pragma unroll
+  for (int kk = 0; kk < E / 2; ++kk) {
+    v[slot(kk)] = cmul(v[slot(kk)], cmul(w, cj(tab[kk])));
+    if (kk + 1 < E / 2) w = cmul(w, u);
+  }
+  w = cmul(z0, ub);
+#pragma unroll
+  for (int kk = -1; kk >= -E / 2; --kk) {
+    v[slot(kk)] = cmul(v[slot(kk)], cmul(w, cj(tab[-kk])));
+    if (kk - 1 >= -E / 2) w = cmul(w, ub);
+  }
+}
+
 __device__ __forceinline__ int xcd_logical_block() {
   // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
   // that consecutive logical ids (adjacent units) run on the same XCD.
@@ -261,9 +291,33 @@ struct RowLds {
 // CJ: 0 (M) or 1 (G) fixed at compile time, -1 read from a.conj.  MID:
 // only the 2-D frequency screen (the screened column passes apply the
 // range-Doppler ones).
-template <class P, int CJ = -1, bool MID = false>
+// Per-line tables of the screens' quadratic factors (apply_quad_tab): for
+// each of the LR lines of a unit and each screen, exp(2 pi i C m^2), m <= E/2.
+template <class P>
+struct RowQTab {
+  static constexpr int NQ = P::E / 2 + 1;
+  static constexpr int PER = 3 * NQ;          // per line
+  static constexpr int size = P::LR * PER;    // per unit
+};
+
+// Fill the tables of unit gi (threads 0 .. LR*PER-1, then a barrier).
+template <class P>
+__device__ __forceinline__ void row_qtab_fill(const RowArgs& a, int gi, float2* qt) {
+  constexpr int NQ = RowQTab<P>::NQ, PER = RowQTab<P>::PER;
+  for (int t = threadIdx.x; t < RowQTab<P>::size; t += P::RT) {
+    const int l = t / PER, sc = (t % PER) / NQ, m = t % NQ;
+    const int r = gi * P::LR + l;
+    const double f2 = a.inv_fs * a.inv_fs;
+    const double p2 = sc == 0 ? a.rowc1[r].x * f2 : (sc == 1 ? a.rowc2[r].x : a.rowc3[r].y * f2);
+    const double C = frac1(p2 * (double)P::T * (double)P::T);  // quad_in_slot's C
+    qt[t] = cis_turns(C * (double)(m * m));
+  }
+  __syncthreads();
+}
+
+template <class P, int CJ = -1, bool MID = false, bool TAB = false>
 __device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane<P>& ln, float2* lds,
-                                         const float2* twl, const TwPowers& hp) {
+                                         const float2* twl, const TwPowers& hp, float2* qt = nullptr) {
   constexpr int HS = hoisted_pass<P>();
   constexpr int N = P::N, E = P::E, T = P::T, LR = P::LR;
   constexpr int LI = RowLds<P>::LI, LS = RowLds<P>::LS;
@@ -286,22 +340,43 @@ __device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane
   int loff = (line / LI) * LS;
   asm volatile("" : "+v"(loff));
   const TwLds tws{twl, twl + 64};
+  // the screens: from per-line tables (TAB) or one FP64 evaluation per element
+  constexpr int NQ = RowQTab<P>::NQ;
+  const float2* qline = qt + line * RowQTab<P>::PER;  // [Phi1, Phi2, Phi3] x NQ
+  auto screen = [&](auto freq, const Quad& q, int sc, float scale) {
+    constexpr bool F = decltype(freq)::value;
+    if constexpr (TAB) apply_quad_tab<E, F>(v, q, qline + sc * NQ, conj, scale);
+    else apply_quad<E, F>(v, q, conj, scale);
+  };
+  using tau_t = std::integral_constant<bool, false>;
+  using freq_t = std::integral_constant<bool, true>;
   // first range-Doppler screen: Phi1 (M) or Phi3* (G)
-  if constexpr (!MID) apply_quad<E, false>(v, conj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), conj, 1.0f);
+  if constexpr (!MID) {
+    if (conj) screen(tau_t{}, phi3_quad(c3, a, b, T), 2, 1.0f);
+    else screen(tau_t{}, phi1_quad(c1, a, b, T), 0, 1.0f);
+  }
   fft_line<P, false, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
-  apply_quad<E, true>(v, phi2_quad(c2, b, T), conj, a.scale);
+  screen(freq_t{}, phi2_quad(c2, b, T), 1, a.scale);
   asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
   fft_line<P, true, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
   // second range-Doppler screen: Phi3 (M) or Phi1* (G)
-  if constexpr (!MID) apply_quad<E, false>(v, conj ? phi1_quad(c1, a, b, T) : phi3_quad(c3, a, b, T), conj, 1.0f);
+  if constexpr (!MID) {
+    if (conj) screen(tau_t{}, phi1_quad(c1, a, b, T), 0, 1.0f);
+    else screen(tau_t{}, phi3_quad(c3, a, b, T), 2, 1.0f);
+  }
 #pragma unroll
   for (int k = 0; k < E; ++k) out.st(v[k], vo, T * k * 32);
 }
+
+#ifndef CSSAR_ROW_QTAB
+#define CSSAR_ROW_QTAB 1
+#endif
 
 template <class P, int CJ, bool MID>
 __global__ __launch_bounds__(P::RT) void row_pass_kernel(RowArgs a) {
   __shared__ float2 lds[RowLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
+  __shared__ float2 qtab[2 * RowQTab<P>::size];  // double-buffered per unit
   load_twiddle_table<P::N>(twl, a.tw);
   __syncthreads();
   const RowLane<P> ln;
@@ -309,14 +384,23 @@ __global__ __launch_bounds__(P::RT) void row_pass_kernel(RowArgs a) {
   if constexpr (hoisted_pass<P>() >= 0)
     hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(ln.b, TwLds{twl, twl + 64});
   const int units = a.na / P::LR;  // N_a is a multiple of LR
-  for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x)
-    row_unit<P, CJ, MID>(a, gi, ln, lds, twl, hp);
+  constexpr bool TAB = CSSAR_ROW_QTAB != 0;
+  int par = 0;
+  for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x) {
+    // the barrier of the fill also orders this unit's table against the
+    // previous reader of the same buffer (two units ago)
+    float2* qt = qtab + par * RowQTab<P>::size;
+    if constexpr (TAB) row_qtab_fill<P>(a, gi, qt);
+    row_unit<P, CJ, MID, TAB>(a, gi, ln, lds, twl, hp, qt);
+    par ^= 1;
+  }
 }
 
 template <class P>
 __global__ __launch_bounds__(P::RT) void row_group_kernel(GroupArgs g) {
   __shared__ float2 lds[RowLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
+  __shared__ float2 qtab[2 * RowQTab<P>::size];
   const RowArgs* __restrict__ args = (const RowArgs*)g.args;
   load_twiddle_table<P::N>(twl, args[0].tw);  // w_N depends on N only
   __syncthreads();
@@ -324,9 +408,14 @@ __global__ __launch_bounds__(P::RT) void row_group_kernel(GroupArgs g) {
   TwPowers hp;
   if constexpr (hoisted_pass<P>() >= 0)
     hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(ln.b, TwLds{twl, twl + 64});
+  constexpr bool TAB = CSSAR_ROW_QTAB != 0;
+  int par = 0;
   for (int u = xcd_logical_block(); u < g.total; u += gridDim.x) {
     const int s = group_find(g.start, g.count, u);
-    row_unit<P>(args[s], u - g.start[s], ln, lds, twl, hp);
+    float2* qt = qtab + par * RowQTab<P>::size;
+    if constexpr (TAB) row_qtab_fill<P>(args[s], u - g.start[s], qt);
+    row_unit<P, -1, false, TAB>(args[s], u - g.start[s], ln, lds, twl, hp, qt);
+    par ^= 1;
   }
 }
 
