@@ -225,3 +225,57 @@ def test_nonfinite_input_is_reported(dev):
         op.sync_status()
     assert ei.value.code == pk.cssar.ENONFINITE
     op.sync_status()  # cleared
+
+
+def test_wide_swath_8192_sampled_columns(dev):
+    # The 8192 x 8192 wide-swath configuration (all state resident): G, G^H
+    # and the first ITA iterate on sampled columns the oracle computes one by
+    # one (its azimuth DFTs are full 8192-point matrix products).
+    shape = (8192, 8192)
+    cols = [0, 1, 4095, 4096, 8191]
+    say(f"[gpu] {shape} operators and X(1), sampled columns")
+    g = csa.Geometry(P, shape)
+    op = _op(shape)
+    x = inputs.random_complex(shape, seed=81)
+    gx = _h(op.apply_G(_d(x, dev)))[:, cols]
+    e1 = rel_l2(gx, csa.G_cols(x, g, cols))
+    del gx
+    mask = inputs.random_mask(shape, 0.5, seed=82)
+    xm = np.where(mask, x, 0)
+    bits = op.pack_mask(torch.from_numpy(mask).to(dev))
+    lam = 0.9
+    x1 = _h(op.ita_solve(_d(xm, dev), bits, lam, 1))[:, cols]
+    e2 = rel_l2(x1, ita.soft_threshold(csa.M_cols(xm, g, cols), lam))
+    say(f"    rel L2 G {e1:.2e}  X(1) {e2:.2e}")
+    assert e1 <= OP_TOL and e2 <= OP_TOL
+
+
+def test_ita_config_2048_points_and_patches(dev):
+    # The 2048 x 2048 single-scene configuration: 200 point targets plus
+    # extended complex-Gaussian patches over 2 % of the pixels (echo through
+    # the oracle's G), 30 % mask, 15 dB, lambda by the sparsity rule; the
+    # first 10 of its iterations against the oracle on the whole image.
+    from oracle import sim
+    wl = inputs.workload("stripmap_2048")
+    shape = wl["shape"]
+    say(f"[gpu] ITA {shape} points + patches, 10 of {wl['iters']} iterations")
+    g = csa.Geometry(P, shape)
+    rows, cols, sig = inputs.point_targets(shape, wl["targets"], seed=wl["seed"])
+    x = inputs.targets_to_image(shape, rows, cols, sig)
+    x = x + inputs.extended_patches(shape, wl["patch_coverage"], seed=wl["seed"] + 1)
+    mask = inputs.random_mask(shape, wl["mask_rate"], seed=wl["seed"] + 2)
+    y = sim.add_noise(csa.G(x, g), mask, wl["snr_db"], inputs.circular_noise(shape, wl["seed"] + 3))
+    lam = ita.lambda_from_sparsity(y, mask, int(np.count_nonzero(x)), g)
+    xr, hr = ita.ita(y, mask, lam, 10, g)
+    op = _op(shape)
+    bits = op.pack_mask(torch.from_numpy(mask).to(dev))
+    xg, hg = op.ita_solve(_d(y, dev), bits, lam, 10, resid=True)
+    e = rel_l2(_h(xg), xr)
+    say(f"    final image rel L2 {e:.2e}")
+    assert e <= IMG_TOL
+    np.testing.assert_allclose(hg.cpu().numpy(), np.array(hr), rtol=1e-4)
+    # the full run stays finite and its residual settles
+    xg, hg = op.ita_solve(_d(y, dev), bits, lam, wl["iters"], resid=True)
+    op.sync_status()
+    h = hg.cpu().numpy()
+    assert np.all(np.isfinite(h)) and h[-1] <= h[0]
