@@ -148,50 +148,16 @@ __device__ __forceinline__ Quad phi2_quad(double2 c, int b, int T) {
 }
 
 // v[k] *= exp(+-2 pi i phase(k')) * s, with k' = k - E/2 (column offset
-// screens) or the signed bin slot (frequency screen: k' = k or k - E).
-//
-// CSSAR_PHASE_REC 1: the slot phases k' = 0, 1, ... and -1, -2, ... follow
-// from k' = 0 by products, z(k' +- 1) = z(k') r(k'), r(k' +- 1) = r(k') q,
-// with z(0) = exp(2 pi i A), r = exp(2 pi i (C +- B)), q = exp(4 pi i C)
-// each evaluated from its FP64 argument (four evaluations per thread and
-// line instead of one per element; the product error grows with |k'| <= E/2).
-// 0: every element's phase from its FP64 argument.
-#ifndef CSSAR_PHASE_REC
-#define CSSAR_PHASE_REC 0
-#endif
-
+// screens) or the signed bin slot (frequency screen: k' = k or k - E); one
+// FP64 evaluation per element.
 template <int E, bool FREQ>
 __device__ __forceinline__ void apply_quad(float2 (&v)[E], const Quad& q, bool conj, float s) {
-#if CSSAR_PHASE_REC
-  // slot of k': column screens k' = k - E/2, frequency screen k' = k or k - E
-  auto slot = [](int kk) { return FREQ ? (kk >= 0 ? kk : kk + E) : kk + E / 2; };
-  auto cj = [&](float2 z) { return conj ? make_float2(z.x, -z.y) : z; };
-  const float2 z0 = cscale(cj(cis_turns(q.A)), s);
-  const float2 qq = cj(cis_turns(2.0 * q.C));
-  float2 z = z0, r = cj(cis_turns(q.B + q.C));
-#pragma unroll
-  for (int kk = 0; kk < E / 2; ++kk) {
-    v[slot(kk)] = cmul(v[slot(kk)], z);
-    if (kk + 1 < E / 2) z = cmul(z, r);
-    if (kk + 2 < E / 2) r = cmul(r, qq);
-  }
-  r = cj(cis_turns(q.C - q.B));
-  z = cmul(z0, r);
-  r = cmul(r, qq);
-#pragma unroll
-  for (int kk = -1; kk >= -E / 2; --kk) {
-    v[slot(kk)] = cmul(v[slot(kk)], z);
-    if (kk - 1 >= -E / 2) z = cmul(z, r);
-    if (kk - 2 >= -E / 2) r = cmul(r, qq);
-  }
-#else
   chunked<E, 4>([&](int k) {
     const int kk = FREQ ? (k < E / 2 ? k : k - E) : k - E / 2;
     float2 p = cis_quad(q, kk);
     p = make_float2(p.x * s, (conj ? -p.y : p.y) * s);
     v[k] = cmul(v[k], p);
   });
-#endif
 }
 
 // The same screen from a per-line table: the slot phase A + B k' + C k'^2
