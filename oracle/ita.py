@@ -66,3 +66,62 @@ def objective(x, y, mask, lam, geom):
     proximal-gradient step with threshold lambda*mu is eq. (th2d)."""
     r = np.asarray(mask, dtype=np.float64) * (y - _csa.G(x, geom))
     return 0.5 * float(np.vdot(r, r).real) + lam * float(np.abs(x).sum())
+
+
+def kth_largest_magnitude(v, r):
+    """|v|_r: the r-th largest magnitude of v (r counted from 1), or 0 when
+    v has fewer than r entries."""
+    a = np.sort(np.abs(np.asarray(v)).ravel())[::-1]
+    return float(a[r - 1]) if 1 <= r <= a.size else 0.0
+
+
+def normalized_step(dx, support, mask, geom):
+    """Step mu_i of Section IV.B (eq. (mure), adaptive form), read as the
+    normalized step of the cited iterative hard thresholding: the printed
+    ratio is inverted, and with it mu_i would be at most 1 and shrink as the
+    mask thins, against the condition 0 < mu^-1 < ||A||^2 it is meant to meet
+    (Section IV.B).  So
+
+        mu = ||dX_G||^2 / ||m o G(dX_G)||^2,
+
+    dX_G = dX on the support G of the current iterate and 0 elsewhere.  It is
+    the exact minimiser of the data term 1/2 ||m o (y - G(X + t dX_G))||^2
+    over t.  With an empty support (the first iteration) the ratio is 0/0;
+    mu = 1 there, which is the same ratio over the whole image (G M = I and
+    M is unitary, so ||m o G M(m o R)|| = ||m o R|| = ||M(m o R)||).  A zero
+    denominator also gives mu = 1."""
+    dxk = np.where(support, np.asarray(dx, dtype=np.complex128), 0.0)
+    num = float(np.vdot(dxk, dxk).real)
+    if num == 0.0:
+        return 1.0
+    gk = np.asarray(mask, dtype=np.float64) * _csa.G(dxk, geom)
+    den = float(np.vdot(gk, gk).real)
+    return num / den if den > 0.0 else 1.0
+
+
+def ita_adaptive(y, mask, k, iters, geom):
+    """Eq. (th2d) with both parameters of Section IV.B set per iteration:
+
+        R      = m o (Y_s - G(X))
+        dX     = M(R)
+        mu_i   = normalized_step(dX, supp X, m)
+        V      = X + mu_i dX                       (= b_mu(X))
+        lambda_i mu_i = |V|_{k+1}                  (the (k+1)-th largest magnitude)
+        X+     = E_{1, lambda_i mu_i}(V)            (keeps the k largest, shrunk)
+
+    Returns (X^(iters), [||R^(i)||^2], [mu_i], [lambda_i])."""
+    y = np.asarray(y, dtype=np.complex128)
+    m = np.asarray(mask, dtype=np.float64)
+    x = np.zeros_like(y)
+    resid, mus, lams = [], [], []
+    for _ in range(int(iters)):
+        r = m * (y - _csa.G(x, geom)) if np.any(x) else m * y
+        resid.append(float(np.vdot(r, r).real))
+        dx = _csa.M(r, geom)
+        mu = normalized_step(dx, x != 0, mask, geom)
+        v = x + mu * dx
+        sigma = kth_largest_magnitude(v, int(k) + 1)
+        x = soft_threshold(v, sigma)
+        mus.append(mu)
+        lams.append(sigma / mu)
+    return x, resid, mus, lams
