@@ -200,6 +200,33 @@ def bench_grad(steps, device):
     }
 
 
+def bench_adaptive(op, y, bits, k, iters, steps, device):
+    """The iteration with the adaptive step and threshold of Section IV.B
+    (cssar_ita_solve_adaptive, sparsity k) on the headline scene: iterations/s
+    and the average duration of each pass kind from per-launch HIP events."""
+    import torch
+    out = torch.empty_like(y)
+    ws = op.workspace(2, device)
+
+    def step():
+        op.ita_solve_adaptive(y, bits, k, iters, out=out, ws=ws)
+
+    t = time_steps(step, steps, 1)
+    op.profile(True)
+    op.profile_read()
+    step()
+    prof = op.profile_read()
+    op.profile(False)
+    _, mu, lam, _ = op.ita_solve_adaptive(y, bits, k, iters, out=out, ws=ws)
+    return {
+        "workload": f"the same scene, k = {k} (its nonzero count), {iters} iterations per step",
+        "iterations_per_s": steps * iters / t,
+        "passes_avg_us": {kind: 1e3 * ms / cnt for kind, (ms, cnt) in prof.items()},
+        "passes_launches": {kind: cnt for kind, (ms, cnt) in prof.items()},
+        "mu_last": float(mu[-1]), "lambda_last": float(lam[-1]),
+    }
+
+
 def time_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -361,6 +388,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-scene batched-versus-plain-loop measurement")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the adaptive step-and-threshold measurement")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the differentiated (forward + reverse pass) measurement")
     ap.add_argument("--no-profile", action="store_true",
@@ -456,6 +485,10 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(dev)
+
+    if not args.no_adaptive:
+        log("bench: adaptive step and threshold")
+        rec["adaptive"] = bench_adaptive(op, y, bits, k, args.iters, 3, dev)
 
     if not args.no_batched:
         rec["batched"] = bench_batched(3, args.iters, dev)

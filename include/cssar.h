@@ -91,6 +91,9 @@ int cssar_destroy_operator(cssar_op* op);
  * start; contents need not be initialised and are clobbered):
  *   mode 0: cssar_apply_G / cssar_apply_GH   (one array in the blocked layout)
  *   mode 1: cssar_ita_solve                  (three arrays in the blocked layout)
+ *   mode 2: cssar_ita_solve_adaptive         (four arrays in the blocked layout, the
+ *           support bits (4 N_a N_r / E bytes, E the column plan's elements per
+ *           thread) and 8.5 KB of selection state)
  * The blocked layout holds 4 x 4 blocks of 128 bytes with a 128-byte pad per
  * block row: (N_a/4) (32 N_r + 128) bytes per array.  Returns 0 for a NULL
  * operator or an unknown mode. */
@@ -119,6 +122,25 @@ int cssar_pack_mask(const cssar_op* op, const void* mask_bytes, void* mask_bits,
  * ws: cssar_workspace_size(op, 1) bytes.  No two of y, x_out, ws may alias. */
 int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda,
                     int iters, void* x_out, float* resid_hist, void* ws, void* stream);
+
+/* Iterative thresholding with both parameters set per iteration as Section
+ * IV.B suggests (eq. (mure) and the threshold rule after it):
+ *   R = m o (y - G X);  dX = M R;
+ *   mu_t = ||dX_G||^2 / ||m o G(dX_G)||^2, dX_G = dX on the support of X
+ *          (the normalized step of the cited iterative hard thresholding; the
+ *          printed ratio is inverted), mu_t = 1 when the support is empty or
+ *          either norm is 0;
+ *   V = X + mu_t dX;  lambda_t mu_t = the (k+1)-th largest |V| (0 when k >= N_a N_r);
+ *   X+ = S_{lambda_t mu_t}(V), which keeps the k largest entries of V.
+ * The selection compares |V|^2 in FP32 (ties at the (k+1)-th value are not
+ * kept).  y, mask_bits, x_out, resid_hist, iters: as cssar_ita_solve; k >= 0
+ * the sparsity (CSSAR_EINVAL if negative); mu_hist, lambda_hist: NULL or
+ * device arrays of iters floats receiving mu_t and lambda_t;
+ * ws: cssar_workspace_size(op, 2) bytes.  No two of y, x_out, ws may alias.
+ * Every step runs on the device; nothing is read back between iterations. */
+int cssar_ita_solve_adaptive(cssar_op* op, const void* y, const void* mask_bits, long k, int iters,
+                             void* x_out, float* mu_hist, float* lambda_hist, float* resid_hist,
+                             void* ws, void* stream);
 
 /* ---------------------------------------------------------------- batch --
  * Many independent scenes (any supported shapes) solved together.  The
@@ -226,10 +248,13 @@ const char* cssar_last_error(void);
  * (conjugate screens, reverse order), 2 column forward azimuth FFT (with
  * optional mask and residual norm), 3 column inverse azimuth FFT, 4 column
  * update + soft-threshold pass, 5 column residual pass, 6 column threshold
- * adjoint, 7 column data adjoint, 8 column iterate adjoint, 9 adjoint row
- * pass with M forward, 10 adjoint row pass with G forward, 11 unused.
+ * adjoint, 7 column data adjoint, 8 column iterate adjoint, 9 column
+ * restricted step (adaptive solver), 10 column masked norm and step, 11
+ * column pre-threshold value, 12 column threshold at the selected value,
+ * 13 adjoint row pass with M forward, 14 adjoint row pass with G forward,
+ * 15 selection of the (k+1)-th largest magnitude (all its launches).
  * ms_sum and counts hold CSSAR_PROFILE_KINDS entries. */
-#define CSSAR_PROFILE_KINDS 12
+#define CSSAR_PROFILE_KINDS 16
 int cssar_profile_enable(cssar_op* op, int on);
 int cssar_profile_read(cssar_op* op, double* ms_sum, long* counts);
 

@@ -99,7 +99,7 @@ def normalized_step(dx, support, mask, geom):
     return num / den if den > 0.0 else 1.0
 
 
-def ita_adaptive(y, mask, k, iters, geom):
+def ita_adaptive(y, mask, k, iters, geom, x0=None):
     """Eq. (th2d) with both parameters of Section IV.B set per iteration:
 
         R      = m o (Y_s - G(X))
@@ -109,10 +109,11 @@ def ita_adaptive(y, mask, k, iters, geom):
         lambda_i mu_i = |V|_{k+1}                  (the (k+1)-th largest magnitude)
         X+     = E_{1, lambda_i mu_i}(V)            (keeps the k largest, shrunk)
 
+    ``x0`` (default 0) is the starting iterate.
     Returns (X^(iters), [||R^(i)||^2], [mu_i], [lambda_i])."""
     y = np.asarray(y, dtype=np.complex128)
     m = np.asarray(mask, dtype=np.float64)
-    x = np.zeros_like(y)
+    x = np.zeros_like(y) if x0 is None else np.array(x0, dtype=np.complex128)
     resid, mus, lams = [], [], []
     for _ in range(int(iters)):
         r = m * (y - _csa.G(x, geom)) if np.any(x) else m * y

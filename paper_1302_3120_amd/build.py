@@ -3,7 +3,8 @@
 The pass kernels of every compiled plan (supported line length and plan
 variant) are compiled from one source (csrc/kern_inst.hip) with different
 CSSAR_N / CSSAR_V, in parallel, then linked with the C-ABI objects
-(csrc/cssar_api.hip, csrc/cssar_batch.hip, csrc/cssar_grad.hip) into
+(csrc/cssar_api.hip, csrc/cssar_batch.hip, csrc/cssar_grad.hip,
+csrc/cssar_adaptive.hip) into
 paper_1302_3120_amd/libcssar.so.
 """
 
@@ -58,7 +59,7 @@ def build(jobs=None, verbose=False, report=False):
         obj = os.path.join(BUILD, f"kern_{n}_{v}.o")
         cmds.append([cc, *flags, *extra, f"-DCSSAR_N={n}", f"-DCSSAR_V={v}", "-c",
                      os.path.join(CSRC, "kern_inst.hip"), "-o", obj])
-    for src in ("cssar_api.hip", "cssar_batch.hip", "cssar_grad.hip"):
+    for src in ("cssar_api.hip", "cssar_batch.hip", "cssar_grad.hip", "cssar_adaptive.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         cmds.append([cc, *flags, "-c", os.path.join(CSRC, src), "-o", obj])
     jobs = jobs or min(len(cmds), max(1, os.cpu_count() or 1))

@@ -1,0 +1,250 @@
+// The iteration of eq. (th2d) with both parameters set per iteration as
+// Section IV.B suggests:
+//
+//   mu_i     = ||dX_G||^2 / ||m o G(dX_G)||^2   (the normalized step of the
+//              cited iterative hard thresholding; the printed ratio is
+//              inverted), dX_G = dX on the support of the iterate,
+//              mu_i = 1 when the support is empty;
+//   lambda_i = |X + mu_i dX|_{k+1} / mu_i       (so the threshold lambda_i mu_i
+//              is the (k+1)-th largest magnitude of V = X + mu_i dX).
+//
+// Per iteration (after the first) the passes are: the row pass of G on F X,
+// the residual column pass, the row pass of M (as in the fixed-parameter
+// solver), then
+//   D: dX on the support -> ||dX_G||^2 and F dX_G;  row pass of G on it;
+//   N: ||m o G dX_G||^2 -> mu_i (device memory);
+//   V: V = X + mu_i dX (spatial);
+//   the selection of the (k+1)-th largest |V|^2: three histogram passes over
+//   V (11, 11 and 10 bits of the FP32 bit pattern, which orders non-negative
+//   floats as their values), each followed by a one-workgroup pass that finds
+//   the bucket holding the rank;
+//   T: X+ = S_sigma(V), the support bits of X+, F X+.
+// Nothing returns to the host between iterations.
+#include <algorithm>
+#include <cmath>
+
+#include "cssar_internal.hpp"
+
+using namespace cssar;
+using namespace cssar::detail;
+
+namespace cssar {
+namespace detail {
+
+constexpr int kSelectThreads = 256;
+constexpr int kFindThreads = 1024;  // two histogram bins per thread
+
+// Bits of |V|^2 resolved by selection level 0, 1, 2 (most significant first).
+__device__ __forceinline__ unsigned level_bin(unsigned key, int level) {
+  return level == 0 ? key >> 21 : level == 1 ? (key >> 10) & 2047u : key & 1023u;
+}
+__device__ __forceinline__ unsigned level_prefix(unsigned key, int level) {
+  return level == 1 ? key >> 21 : key >> 10;  // bits fixed by the earlier levels
+}
+
+// Histogram of the keys |V|^2 (FP32 bits; V in the blocked layout, pads
+// skipped) at one level, over the keys that match the prefix found so far.
+__global__ __launch_bounds__(kSelectThreads) void select_hist_kernel(const float4* __restrict__ v, int na,
+                                                                     int nr, AdaptState* st, int level) {
+  __shared__ unsigned h[2048];
+  for (int i = threadIdx.x; i < 2048; i += kSelectThreads) h[i] = 0u;
+  __syncthreads();
+  if (st->done) return;  // fewer than k + 1 keys: nothing to select
+  const unsigned prefix = st->prefix;
+  const unsigned per_row = 2u * (unsigned)nr;      // float4 (two elements) per block row
+  const unsigned stride = b4_stride(nr) / 16u;     // block-row stride in float4
+  const unsigned total = (unsigned)(na / 4) * per_row;
+  for (unsigned q = blockIdx.x * kSelectThreads + threadIdx.x; q < total; q += gridDim.x * kSelectThreads) {
+    const unsigned row = q / per_row;
+    const float4 p = v[row * stride + (q - row * per_row)];
+    const unsigned k0 = __float_as_uint(fmaf(p.x, p.x, p.y * p.y));
+    const unsigned k1 = __float_as_uint(fmaf(p.z, p.z, p.w * p.w));
+    if (level == 0 || level_prefix(k0, level) == prefix) atomicAdd(&h[level_bin(k0, level)], 1u);
+    if (level == 0 || level_prefix(k1, level) == prefix) atomicAdd(&h[level_bin(k1, level)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2048; i += kSelectThreads)
+    if (h[i]) atomicAdd(&st->hist[i], h[i]);
+}
+
+// One workgroup: the bucket of this level that holds the rank-th largest
+// key (counting from the top bucket down), the rank left inside it, and the
+// histogram cleared for the next level.  After the last level the key is
+// sigma^2; sigma, lambda = sigma / mu (into lambda_out if not NULL) and the
+// selection state for the next iteration follow.
+__global__ __launch_bounds__(kFindThreads) void select_find_kernel(AdaptState* st, int level,
+                                                                   float* lambda_out) {
+  __shared__ unsigned suf[kFindThreads];
+  const int t = threadIdx.x;
+  const unsigned h0 = st->hist[2 * t], h1 = st->hist[2 * t + 1];
+  st->hist[2 * t] = 0u;
+  st->hist[2 * t + 1] = 0u;
+  const bool done = st->done != 0u;
+  const unsigned rank = st->rank;
+  // suffix sums over the threads: suf[t] = keys in bins >= 2 t
+  suf[t] = h0 + h1;
+  __syncthreads();
+  for (int off = 1; off < kFindThreads; off <<= 1) {
+    const unsigned add = t + off < kFindThreads ? suf[t + off] : 0u;
+    __syncthreads();
+    suf[t] += add;
+    __syncthreads();
+  }
+  const unsigned above = suf[t] - h0 - h1;  // keys in bins > 2 t + 1
+  unsigned bin = 0xFFFFFFFFu, left = 0u;
+  if (!done) {
+    if (above < rank && above + h1 >= rank) {
+      bin = 2u * t + 1u;
+      left = rank - above;
+    } else if (above + h1 < rank && above + h1 + h0 >= rank) {
+      bin = 2u * t;
+      left = rank - above - h1;
+    }
+  }
+  const bool too_few = level == 0 && suf[0] < rank;  // (uniform)
+  if (t == 0 && too_few && !done) {
+    st->done = 1u;
+    st->sigma2 = 0.0f;
+    st->sigma = 0.0f;
+  }
+  if (bin != 0xFFFFFFFFu) {
+    if (level < 2) {
+      st->prefix = level == 0 ? bin : (st->prefix << 11) | bin;
+      st->rank = left;
+    } else {
+      const float s2 = __uint_as_float((st->prefix << 10) | bin);
+      const float sg = sqrtf(s2);
+      st->sigma2 = s2;
+      st->sigma = sg;
+      if (lambda_out) lambda_out[0] = sg / st->mu;
+    }
+  }
+  if (level == 2) {
+    __syncthreads();  // (the thread that found the bin has read the prefix)
+    if (t == 0) {
+      if (done && lambda_out) lambda_out[0] = 0.0f;  // threshold 0
+      st->prefix = 0u;
+      st->rank = st->k1;
+      st->done = 0u;
+    }
+  }
+}
+
+// Selection state at the start of a solve: mu_0 = 1 (the support of X(0) = 0
+// is empty), histogram cleared, rank k + 1.
+__global__ void adapt_init_kernel(AdaptState* st, unsigned k1, float* mu0) {
+  for (int i = threadIdx.x; i < 2048; i += blockDim.x) st->hist[i] = 0u;
+  if (threadIdx.x == 0) {
+    st->prefix = 0u;
+    st->rank = k1;
+    st->k1 = k1;
+    st->done = 0u;
+    st->mu = 1.0f;
+    st->sigma = 0.0f;
+    st->sigma2 = 0.0f;
+    st->num = 0.0;
+    if (mu0) mu0[0] = 1.0f;
+  }
+}
+
+// Bytes of the support bits of the adaptive column passes (one word per
+// thread and column tile).
+size_t support_bytes(const cssar_op* op) {
+  const KernelTable* kt = op->kcol[CK_T];
+  return (size_t)(op->nr / kt->C) * kt->CT * sizeof(uint32_t);
+}
+
+int select_threshold(cssar_op* op, const float2* V, AdaptState* st, float* lambda_out, hipStream_t s) {
+  const int grid = std::max(1, std::min(op->cus * 4, (op->na / 4) * op->nr / 2 / kSelectThreads + 1));
+  return timed(op, 15, s, [&] {
+    for (int level = 0; level < 3; ++level) {
+      hipLaunchKernelGGL(select_hist_kernel, dim3(grid), dim3(kSelectThreads), 0, s, (const float4*)V, op->na,
+                         op->nr, st, level);
+      hipLaunchKernelGGL(select_find_kernel, dim3(1), dim3(kFindThreads), 0, s, st, level,
+                         level == 2 ? lambda_out : nullptr);
+    }
+    return hipGetLastError();
+  });
+}
+
+}  // namespace detail
+}  // namespace cssar
+
+extern "C" {
+
+int cssar_ita_solve_adaptive(cssar_op* op, const void* y, const void* mask_bits, long k, int iters,
+                             void* x_out, float* mu_hist, float* lambda_hist, float* resid_hist, void* ws,
+                             void* stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (!y || !mask_bits || !x_out || !ws) return fail(CSSAR_EINVAL, "NULL array");
+  if (iters < 1) return fail(CSSAR_EINVAL, "iters must be >= 1");
+  if (k < 0) return fail(CSSAR_EINVAL, "k must be >= 0");
+  if (x_out == y || x_out == ws || ws == y) return fail(CSSAR_EINVAL, "x_out, y and ws must not alias");
+  const long n = (long)op->na * op->nr;
+  const unsigned k1 = (unsigned)std::min(k, n) + 1u;  // ranks beyond n select nothing
+  hipStream_t s = (hipStream_t)stream;
+  const size_t blk = align256(b4_bytes(op->na, op->nr));
+  char* w = (char*)ws;
+  float2* X = (float2*)w;             // F_eta X (blocked layout)
+  float2* P = (float2*)(w + blk);     // pass buffer; V in place of F_eta dX
+  float2* Y = (float2*)(w + 2 * blk); // m o y (blocked layout, unsampled marked)
+  float2* Q = (float2*)(w + 3 * blk); // F_eta dX_G, then F_eta G dX_G
+  uint32_t* supp = (uint32_t*)(w + 4 * blk);
+  AdaptState* st = (AdaptState*)(w + 4 * blk + align256(support_bytes(op)));
+  hipLaunchKernelGGL(adapt_init_kernel, dim3(1), dim3(256), 0, s, st, k1, mu_hist);
+  HIP_TRY(hipGetLastError());
+  ColArgs a = col_args(op);
+  a.y = Y;
+  a.mask = (const uint32_t*)mask_bits;
+  a.ad = st;
+  a.supp = supp;
+  for (int t = 0; t < iters; ++t) {
+    const bool last = t == iters - 1;
+    a.hist_out = resid_hist ? resid_hist + t : nullptr;
+    if (t == 0) {
+      ColArgs f = a;  // R(0) = m o y: P = F_eta R, keep m o y
+      f.in0 = (const float2*)y;
+      f.out = P;
+      f.out2 = Y;
+      f.flags = 1 | 4;
+      if ((rc = launch_col(op, CK_FWD, f, s))) return rc;
+    } else {
+      if ((rc = launch_row(op, row_args(op, X, P, 1), s))) return rc;
+      ColArgs r = a;
+      r.in0 = P;
+      r.out = P;
+      if ((rc = launch_col(op, CK_R, r, s))) return rc;
+    }
+    if ((rc = launch_row(op, row_args(op, P, P, 0), s))) return rc;  // P = F_eta dX
+    if (t > 0) {
+      ColArgs d = a;  // Q = F_eta dX_G, ||dX_G||^2
+      d.in0 = P;
+      d.out = Q;
+      d.hist_out = nullptr;
+      if ((rc = launch_col(op, CK_D, d, s))) return rc;
+      if ((rc = launch_row(op, row_args(op, Q, Q, 1), s))) return rc;
+      ColArgs m = a;  // mu = ||dX_G||^2 / ||m o G dX_G||^2
+      m.in0 = Q;
+      m.hist_out = mu_hist ? mu_hist + t : nullptr;
+      if ((rc = launch_col(op, CK_N, m, s))) return rc;
+    }
+    ColArgs v = a;  // V = X + mu dX (spatial, into P)
+    v.in0 = X;
+    v.in1 = P;
+    v.out = P;
+    v.flags = t == 0 ? 1 : 0;
+    v.hist_out = nullptr;
+    if ((rc = launch_col(op, CK_V, v, s))) return rc;
+    if ((rc = select_threshold(op, P, st, lambda_hist ? lambda_hist + t : nullptr, s))) return rc;
+    ColArgs x = a;  // X+ = S_sigma(V), support bits, F_eta X+ (or X+ at the end)
+    x.in0 = P;
+    x.out = last ? (float2*)x_out : X;
+    x.flags = last ? 2 : 0;
+    x.hist_out = nullptr;
+    if ((rc = launch_col(op, CK_T, x, s))) return rc;
+  }
+  return CSSAR_OK;
+}
+
+}  // extern "C"

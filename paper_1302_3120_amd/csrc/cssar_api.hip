@@ -168,24 +168,6 @@ hipEvent_t take_event(cssar_op* op) {
   return e;
 }
 
-// Kind ids of cssar_profile_read: 0/1 row pass (M / G chain), 2 + column kernel id.
-template <typename F>
-int timed(cssar_op* op, int kind, hipStream_t s, F&& launch) {
-  hipEvent_t a = nullptr, b = nullptr;
-  if (op->profiling) {
-    a = take_event(op);
-    b = take_event(op);
-    if (!a || !b) return fail(CSSAR_EHIP, "hipEventCreate failed");
-    HIP_TRY(hipEventRecord(a, s));
-  }
-  HIP_TRY(launch());
-  if (op->profiling) {
-    HIP_TRY(hipEventRecord(b, s));
-    op->recs.push_back({kind, a, b});
-  }
-  return CSSAR_OK;
-}
-
 int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s) {
   return timed(op, a.conj ? 1 : 0, s, [&] { return op->kr->row(a, op->grid_row, s); });
 }
@@ -204,7 +186,7 @@ int launch_col_scr(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
 }
 
 int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s) {
-  return timed(op, 9 + conj, s, [&] { return op->kr->row_adj[conj](a, op->grid_adj[conj], s); });
+  return timed(op, 13 + conj, s, [&] { return op->kr->row_adj[conj](a, op->grid_adj[conj], s); });
 }
 
 }  // namespace detail
@@ -322,6 +304,8 @@ size_t cssar_workspace_size(const cssar_op* op, int mode) {
       return blk;
     case 1:
       return 3 * blk;
+    case 2:
+      return 4 * blk + align256(support_bytes(op)) + align256(sizeof(AdaptState));
     default:
       return 0;
   }

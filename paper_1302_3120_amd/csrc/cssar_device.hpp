@@ -503,12 +503,13 @@ __device__ __forceinline__ float block_sum(float x, float* red) {
   return s;
 }
 
-// Partial written by every block; the last block to finish sums the partials
-// in FP64 (thread t takes partials t, t + 256, ... in order, then a fixed
-// tree), so the result does not depend on completion order.  counter is
-// reset for the next use.
-__device__ __forceinline__ void finish_partials(float part, float* partials, unsigned* counter,
-                                                float* out, unsigned* status, int nblocks) {
+// Last-block-done reduction of one float per block: every block stores its
+// partial; the block that finishes last sums them in FP64 in a fixed order
+// (thread t takes partials t, t + 256, ... in order, then a fixed tree) and
+// returns true with the total in total (the same in all its threads); the
+// others return false.  counter is reset for the next use.
+__device__ __forceinline__ bool last_block_total(float part, float* partials, unsigned* counter,
+                                                 int nblocks, double& total) {
   __shared__ int is_last;
   __shared__ double sh[256];
   if (threadIdx.x == 0) {
@@ -518,7 +519,7 @@ __device__ __forceinline__ void finish_partials(float part, float* partials, uns
     is_last = (done == (unsigned)(nblocks - 1));
   }
   __syncthreads();
-  if (!is_last) return;
+  if (!is_last) return false;
   __threadfence();
   // (slots are strided over the threads, so any block size works)
   for (int t = threadIdx.x; t < 256; t += blockDim.x) {
@@ -531,11 +532,20 @@ __device__ __forceinline__ void finish_partials(float part, float* partials, uns
     for (int t = threadIdx.x; t < w; t += blockDim.x) sh[t] += sh[t + w];
     __syncthreads();
   }
+  total = sh[0];
+  if (threadIdx.x == 0) atomicExch(counter, 0u);
+  return true;
+}
+
+// The total of last_block_total into out[0] (if out is not NULL); sets bit 0
+// of status when it is not finite.
+__device__ __forceinline__ void finish_partials(float part, float* partials, unsigned* counter,
+                                                float* out, unsigned* status, int nblocks) {
+  double s;
+  if (!last_block_total(part, partials, counter, nblocks, s)) return;
   if (threadIdx.x == 0) {
-    const double s = sh[0];
     if (out) out[0] = (float)s;
     if (!isfinite(s)) atomicOr(status, 1u);
-    atomicExch(counter, 0u);
   }
 }
 

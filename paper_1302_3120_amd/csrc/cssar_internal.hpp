@@ -73,12 +73,37 @@ ColArgs col_args(const cssar_op* op);
 RowArgs row_args(const cssar_op* op, const void* in, void* out, int conj);
 int check_op(const cssar_op* op);
 
+// An event from the operator's pool (created when the pool is empty).
+hipEvent_t take_event(cssar_op* op);
+// Runs launch(), bracketed by two events on s when profiling is on.  Kind ids
+// of cssar_profile_read: 0/1 row pass (M / G chain), 2 + column kernel id,
+// 13/14 adjoint row pass (M / G forward), 15 selection of the adaptive threshold.
+template <typename F>
+inline int timed(cssar_op* op, int kind, hipStream_t s, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (op->profiling) {
+    a = take_event(op);
+    b = take_event(op);
+    if (!a || !b) return fail(CSSAR_EHIP, "hipEventCreate failed");
+    HIP_TRY(hipEventRecord(a, s));
+  }
+  HIP_TRY(launch());
+  if (op->profiling) {
+    HIP_TRY(hipEventRecord(b, s));
+    op->recs.push_back({kind, a, b});
+  }
+  return CSSAR_OK;
+}
+
 // Launch a pass kernel of the operator (timed when profiling is on).
 int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s);
 int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s);
 int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s);
 int launch_row_mid(cssar_op* op, const RowArgs& a, hipStream_t s);
 int launch_col_scr(cssar_op* op, int which, const ColArgs& a, hipStream_t s);
+
+// Bytes of the support bits of the adaptive solver's column passes.
+size_t support_bytes(const cssar_op* op);
 
 // Per Doppler bin, the derivatives of the three phase arguments (radians)
 // with respect to K_a and K_r as polynomials of the centred column offset

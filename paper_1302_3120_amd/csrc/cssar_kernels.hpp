@@ -9,6 +9,11 @@
 //     INV:  / N_a -> F_eta^-1
 //     A:    V = F_eta^-1[Xt + mu Z] / N_a -> X+ = S_sigma(V) -> F_eta X+ (or X+)
 //     R:    GX = F_eta^-1[W] / N_a -> R = m o y - m o GX, ||R||^2 -> F_eta R
+//   adaptive parameters (Section IV.B):
+//     D:    dX = F_eta^-1[Z] / N_a -> dX on the support, ||.||^2 -> F_eta of it
+//     N:    F_eta^-1[W] / N_a -> ||m o .||^2 -> the step mu = ||dX_G||^2 / that
+//     V:    V = F_eta^-1[Xt + mu Z] / N_a (mu from device memory)
+//     T:    X+ = S_sigma(V) (sigma from device memory), support bits -> F_eta X+
 //
 // All three phase screens are evaluated in the row passes, where each is a
 // quadratic polynomial in the element's offset along the line.
@@ -84,7 +89,28 @@ struct RowArgs {
 // Column modes.  FWD, INV, A, R: the forward passes.  VB, U, XB: the
 // adjoint passes of the gradient (threshold adjoint, data adjoint, update
 // of the iterate's adjoint).
-enum ColMode { COL_FWD = 0, COL_INV = 1, COL_A = 2, COL_R = 3, COL_VB = 4, COL_U = 5, COL_XB = 6 };
+// D, N, V, T: the passes of the adaptive step and threshold.
+enum ColMode {
+  COL_FWD = 0, COL_INV = 1, COL_A = 2, COL_R = 3, COL_VB = 4, COL_U = 5, COL_XB = 6,
+  COL_D = 7, COL_N = 8, COL_V = 9, COL_T = 10
+};
+
+// Device-resident state of the adaptive solver (one per solve, in its
+// workspace): the selection of the (k+1)-th largest |V|^2 by its FP32 bit
+// pattern (11 + 11 + 10 bits, most significant first), and the step and
+// threshold of the current iteration.
+struct AdaptState {
+  unsigned hist[2048];  // histogram of the current selection level (cleared after use)
+  unsigned prefix;      // key bits selected so far
+  unsigned rank;        // rank still to find among the keys under prefix (1 = largest)
+  unsigned k1;          // k + 1
+  unsigned done;        // fewer than k + 1 keys: the threshold is 0
+  float mu;             // step of the current iteration
+  float sigma;          // threshold lambda mu of the current iteration
+  float sigma2;         // sigma^2, the selected key
+  float pad;
+  double num;           // ||dX_G||^2 of the current iteration
+};
 
 // Marks an unsampled entry of the stored copy of m o y (real part; a NaN
 // with a payload that arithmetic does not produce).
@@ -114,6 +140,10 @@ struct ColArgs {
   const double2* rowc1;  // per Doppler bin: Phi1 (a1, d1)
   const double2* rowc3;  //                  Phi3 (D, b3)
   double inv_fs, fc_fs, p_c;
+  // adaptive passes
+  AdaptState* ad;        // step, threshold, ||dX_G||^2
+  uint32_t* supp;        // D (read), T (written): support bits, word tile * CT + thread,
+                         // bit k = element (b + T k, tile C + c) of the column tile
 };
 
 // Elementwise work on the E register elements in chunks of CH, with
@@ -547,6 +577,17 @@ __device__ __forceinline__ void col_screen(float2 (&v)[P::E], const ColArgs& a, 
   });
 }
 
+// Packed sampling mask: bit e % 32 of word e / 32, e = blocked element index
+// of (i, j).  Byte offset and bit of element (b, j), and the byte step per k
+// (element b + T k; T N_r is a multiple of 32).
+struct MaskAddr {
+  uint32_t moff, bit, kstep;
+};
+__device__ __forceinline__ MaskAddr mask_addr(int b, int j, int T, int nr) {
+  const uint32_t e0 = (((uint32_t)(b >> 2) * (nr / 4) + (j >> 2)) << 4) + ((b & 3) << 2) + (j & 3);
+  return {(e0 >> 5) * 4u, e0 & 31u, (uint32_t)T * (uint32_t)nr / 32u * 4u};
+}
+
 // SCR (screened passes of the solver): the residual pass applies Phi1* on
 // input and Phi1 on output, the update pass Phi3 on input and Phi3* on its
 // azimuth-spectrum output, the first forward pass Phi1 on output; the row
@@ -560,19 +601,20 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
   constexpr int N = P::N, E = P::E, T = P::T, C = P::C;
   const uint32_t rmb = clamp_bytes((size_t)N * a.nr * 8), b4b = clamp_bytes(b4_bytes(N, a.nr));
   constexpr int in_layout = MODE == COL_FWD ? RM : B4;
-  const int out_layout = (MODE == COL_INV || (MODE == COL_A && (a.flags & 2))) ? RM : B4;
+  const int out_layout =
+      (MODE == COL_INV || ((MODE == COL_A || MODE == COL_T) && (a.flags & 2))) ? RM : B4;
   const Buf in0(a.in0, in_layout == RM ? rmb : b4b), in1(a.in1, b4b), yb(a.y, b4b);
   const Buf out(a.out, out_layout == RM ? rmb : b4b), out2(a.out2, b4b);
-  const bool first = (MODE == COL_A || MODE == COL_VB) && (a.flags & 1);
+  const bool first = (MODE == COL_A || MODE == COL_VB || MODE == COL_V) && (a.flags & 1);
   const int j = tile * C + c;
   const Addr ai = col_addr(in_layout, b, j, T, a.nr);
   const Addr ab = col_addr(B4, b, j, T, a.nr);
   float acc = 0.f;
   float2 v[E], y2[E];
   float2 y3[(MODE == COL_VB || MODE == COL_U || MODE == COL_XB) ? E : 1];
-  if constexpr (MODE == COL_A || MODE == COL_VB) {
+  if constexpr (MODE == COL_A || MODE == COL_VB || MODE == COL_V) {
     // V = F^-1[Xt + mu Z] / N_a
-    const float ms = a.mu * a.scale;
+    const float ms = (MODE == COL_V ? a.ad->mu : a.mu) * a.scale;
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = cscale(in1.f2(ai.voff, k * ai.kstep), ms);
     if (!first) {
@@ -589,7 +631,7 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
 #pragma unroll
       for (int k = 0; k < E; ++k) y3[k] = yb.f2(ab.voff, k * ab.kstep);  // Xbar of X+
     }
-  } else if constexpr (MODE == COL_FWD) {
+  } else if constexpr (MODE == COL_FWD || MODE == COL_T) {
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = in0.f2(ai.voff, k * ai.kstep);
   } else {
@@ -614,14 +656,11 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
   if constexpr (MODE == COL_FWD) {
     if (a.flags & 1) {
       const Buf mask(a.mask, clamp_bytes(((size_t)N * a.nr + 31) / 32 * 4));
-      const uint32_t kmask = T * (uint32_t)a.nr / 32 * 4;  // mask byte step per k (T N_r % 32 == 0)
-      // blocked element index of (b, j) addresses the packed mask
-      const uint32_t e0 = (((uint32_t)(b >> 2) * (a.nr / 4) + (j >> 2)) << 4) + ((b & 3) << 2) + (j & 3);
-      const uint32_t moff = (e0 >> 5) * 4u, bit = e0 & 31u;
+      const MaskAddr ma = mask_addr(b, j, T, a.nr);
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        const uint32_t w = mask.u32(moff, k * kmask);
-        const bool keep = (w >> bit) & 1u;
+        const uint32_t w = mask.u32(ma.moff, k * ma.kstep);
+        const bool keep = (w >> ma.bit) & 1u;
         if (!keep) v[k] = make_float2(0.f, 0.f);
         acc = fmaf(v[k].x, v[k].x, fmaf(v[k].y, v[k].y, acc));
         if (a.flags & 4)
@@ -687,6 +726,46 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
     fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = cadd(y3[k], v[k]);
+  } else if constexpr (MODE == COL_D) {
+    // dX = F^-1[Z] / N_a; dX_G = dX on the support of the iterate; out = F dX_G
+    static_assert(E <= 32, "support word holds E bits");
+    fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
+    const uint32_t w = a.supp[(uint32_t)tile * P::CT + threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      if (!((w >> k) & 1u)) v[k] = make_float2(0.f, 0.f);
+      acc = fmaf(v[k].x, v[k].x, fmaf(v[k].y, v[k].y, acc));
+    }
+    asm volatile("" : "+v"(lb), "+v"(lc));
+    fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
+  } else if constexpr (MODE == COL_N) {
+    // g = F^-1[W] / N_a (= G dX_G); ||m o g||^2 (no output)
+    fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
+    const Buf mask(a.mask, clamp_bytes(((size_t)N * a.nr + 31) / 32 * 4));
+    const MaskAddr ma = mask_addr(b, j, T, a.nr);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const bool keep = (mask.u32(ma.moff, k * ma.kstep) >> ma.bit) & 1u;
+      const float e2 = fmaf(v[k].x, v[k].x, v[k].y * v[k].y);
+      acc += keep ? e2 : 0.f;
+    }
+  } else if constexpr (MODE == COL_V) {
+    fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);  // V (spatial)
+  } else if constexpr (MODE == COL_T) {
+    // X+ = S_sigma(V): kept where |V|^2 > sigma^2 (sigma^2 the selected
+    // (k+1)-th largest |V|^2, computed the same way); support bit = X+ != 0
+    static_assert(E <= 32, "support word holds E bits");
+    const float sg = a.ad->sigma, s2 = a.ad->sigma2;
+    uint32_t w = 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const float m2 = fmaf(v[k].x, v[k].x, v[k].y * v[k].y);
+      const float f = m2 > s2 ? fmaxf(fmaf(-sg, rsqrtf(m2), 1.0f), 0.0f) : 0.0f;
+      v[k] = cscale(v[k], f);
+      w |= (f > 0.0f ? 1u : 0u) << k;
+    }
+    a.supp[(uint32_t)tile * P::CT + threadIdx.x] = w;
+    if (!(a.flags & 2)) fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
   } else {  // COL_R: GX = F^-1[W] / N_a; R = m o y - m o GX; out = F R
     fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
     // split plans, screened passes: m o y in chunks of 8 after the transform
@@ -718,9 +797,11 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
   if constexpr (SCR && MODE == COL_A) {
     if (!(a.flags & 2)) col_screen<P, 3, true>(v, a, b, j);
   }
-  const Addr ao = out_layout == RM ? col_addr(RM, b, j, T, a.nr) : ab;
+  if constexpr (MODE != COL_N) {
+    const Addr ao = out_layout == RM ? col_addr(RM, b, j, T, a.nr) : ab;
 #pragma unroll
-  for (int k = 0; k < E; ++k) out.st(v[k], ao.voff, k * ao.kstep);
+    for (int k = 0; k < E; ++k) out.st(v[k], ao.voff, k * ao.kstep);
+  }
   return acc;
 }
 
@@ -767,6 +848,25 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   if constexpr (MODE == COL_VB) {
     const float part = block_sum<CT>(acc, red);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = part;  // reduced by reduce_partials_kernel
+  }
+  if constexpr (MODE == COL_D || MODE == COL_N) {
+    // D: ||dX_G||^2; N: ||m o G dX_G||^2 and the step (Section IV.B, eq. (mure)
+    // read as the normalized step): mu = ||dX_G||^2 / ||m o G dX_G||^2, and
+    // mu = 1 when either is 0 (empty support: the same ratio over the whole
+    // image is 1 because G M = I and M is unitary)
+    const float part = block_sum<CT>(acc, red);
+    double tot;
+    if (last_block_total(part, a.partials, a.counter, gridDim.x, tot) && threadIdx.x == 0) {
+      if (!isfinite(tot)) atomicOr(a.status, 1u);
+      if constexpr (MODE == COL_D) {
+        a.ad->num = tot;
+      } else {
+        const double num = a.ad->num;
+        const double mu = (num == 0.0 || !(tot > 0.0)) ? 1.0 : num / tot;
+        a.ad->mu = (float)mu;
+        if (a.hist_out) a.hist_out[0] = (float)mu;
+      }
+    }
   }
 }
 

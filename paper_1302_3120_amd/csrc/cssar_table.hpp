@@ -13,7 +13,8 @@ struct ColArgs;
 struct GroupArgs;
 
 // Column kernels: the first CK_GROUPED also exist as grouped (batched) kernels.
-enum ColKernel { CK_FWD = 0, CK_INV, CK_A, CK_R, CK_VB, CK_U, CK_XB, CK_COUNT };
+// CK_D .. CK_T: the adaptive step and threshold passes.
+enum ColKernel { CK_FWD = 0, CK_INV, CK_A, CK_R, CK_VB, CK_U, CK_XB, CK_D, CK_N, CK_V, CK_T, CK_COUNT };
 constexpr int CK_GROUPED = 4;
 
 struct KernelTable {

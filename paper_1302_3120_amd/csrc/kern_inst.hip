@@ -23,7 +23,8 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
       &K::row,
       {&K::template col<COL_FWD>, &K::template col<COL_INV>, &K::template col<COL_A>,
        &K::template col<COL_R>, &K::template col<COL_VB>, &K::template col<COL_U>,
-       &K::template col<COL_XB>},
+       &K::template col<COL_XB>, &K::template col<COL_D>, &K::template col<COL_N>,
+       &K::template col<COL_V>, &K::template col<COL_T>},
       &K::row_group,
       {&K::template col_group<COL_FWD>, &K::template col_group<COL_INV>,
        &K::template col_group<COL_A>, &K::template col_group<COL_R>},
@@ -38,7 +39,11 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_R, false>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_VB, false>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_U, false>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_XB, false>)},
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_XB, false>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_D, false>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_N, false>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_V, false>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_T, false>)},
       reinterpret_cast<const void*>(&row_group_kernel<P>),
       {reinterpret_cast<const void*>(&col_group_kernel<P, COL_FWD>),
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_INV>),

@@ -27,12 +27,14 @@ SYMBOLS = (
     "cssar_make_batch", "cssar_destroy_batch", "cssar_batch_workspace_size",
     "cssar_batch_set_graph", "cssar_batch_autotune", "cssar_batch_describe",
     "cssar_ita_solve_batched", "cssar_checkpoint_size", "cssar_grad_workspace_size",
-    "cssar_ita_forward", "cssar_ita_backward",
+    "cssar_ita_forward", "cssar_ita_backward", "cssar_ita_solve_adaptive",
 )
 
 PROFILE_KINDS = ("row_M", "row_G", "col_fwd", "col_inv", "col_update_threshold",
                  "col_residual", "col_threshold_adjoint", "col_data_adjoint",
-                 "col_iterate_adjoint", "row_adjoint_M", "row_adjoint_G", "unused11")
+                 "col_iterate_adjoint", "col_restricted_step", "col_step_norm",
+                 "col_value", "col_threshold_selected", "row_adjoint_M", "row_adjoint_G",
+                 "select_kth")
 NK = len(PROFILE_KINDS)
 
 
@@ -100,6 +102,8 @@ def lib():
         L.cssar_grad_workspace_size.restype = ctypes.c_size_t
         L.cssar_ita_forward.argtypes = [vp, vp, vp, f, i, i, vp, vp, vp, vp]
         L.cssar_ita_backward.argtypes = [vp, vp, vp, f, i, i, vp, vp, vp, vp, vp, vp]
+        L.cssar_ita_solve_adaptive.argtypes = [vp, vp, vp, ctypes.c_long, i, vp, vp, vp, vp, vp, vp]
+        L.cssar_ita_solve_adaptive.restype = ctypes.c_int
         L.cssar_ita_forward.restype = ctypes.c_int
         L.cssar_ita_backward.restype = ctypes.c_int
         for name in ("cssar_make_operator", "cssar_destroy_operator", "cssar_apply_G",
@@ -233,6 +237,22 @@ class Operator:
                                      _ptr(hist) if hist is not None else None,
                                      _ptr(ws), _stream()))
         return (out, hist) if resid else out
+
+    def ita_solve_adaptive(self, y, mask_bits, k, iters, out=None, ws=None):
+        """Iterative thresholding with the step and threshold of Section IV.B
+        set per iteration from the sparsity k (cssar_ita_solve_adaptive).
+        Returns (X^(iters), mu_t, lambda_t, ||R^(t)||^2), the last three as
+        float32 device tensors of iters entries."""
+        y = self._arr(y, "y")
+        if mask_bits.dtype != torch.int32 or not mask_bits.is_cuda:
+            raise TypeError("mask_bits must come from pack_mask")
+        out = torch.empty_like(y) if out is None else self._arr(out, "out")
+        ws = self._ws(ws, 2, y.device)
+        hists = [torch.empty(int(iters), dtype=torch.float32, device=y.device) for _ in range(3)]
+        _check(lib().cssar_ita_solve_adaptive(self._h, _ptr(y), _ptr(mask_bits), int(k), int(iters),
+                                              _ptr(out), *(_ptr(h) for h in hists), _ptr(ws),
+                                              _stream()))
+        return (out, *hists)
 
     def ita_forward(self, y, mask_bits, lam, iters, every, out=None):
         """cssar_ita_forward: X^(iters) and the checkpoint buffer for the

@@ -95,6 +95,9 @@ def test_null_arguments(L):
     assert L.cssar_apply_G(None, None, None, None, None) == -1
     assert L.cssar_apply_GH(None, None, None, None, None) == -1
     assert L.cssar_ita_solve(None, None, None, 0.1, 10, None, None, None, None) == -1
+    assert L.cssar_ita_solve_adaptive(None, None, None, 10, 10, None, None, None, None, None,
+                                      None) == -1
+    assert L.cssar_workspace_size(None, 2) == 0
     assert L.cssar_pack_mask(None, None, None, None) == -1
     assert L.cssar_sync_status(None, None) == -1
     assert L.cssar_destroy_operator(None) == 0
