@@ -227,6 +227,33 @@ def bench_adaptive(op, y, bits, k, iters, steps, device):
     }
 
 
+def bench_rda(shape, y, bits, lam, iters, steps, device):
+    """The fixed-parameter iteration with the range-Doppler operator of
+    eq. (RDA) (8-tap truncated-sinc migration correction) on the headline
+    scene: iterations/s and the average duration of each pass kind."""
+    import torch
+    import inputs
+    import paper_1302_3120_amd as pk
+    op = pk.make_operator(inputs.RADAR_STRIPMAP, shape, chain="rda", taps=8)
+    out = torch.empty_like(y)
+    ws = op.workspace(1, device)
+
+    def step():
+        op.ita_solve(y, bits, lam, iters, out=out, ws=ws)
+
+    t = time_steps(step, steps, 1)
+    op.profile(True)
+    op.profile_read()
+    step()
+    prof = op.profile_read()
+    op.profile(False)
+    return {
+        "workload": f"the same scene and lambda, range-Doppler G and M (8 taps), {iters} iterations per step",
+        "iterations_per_s": steps * iters / t,
+        "passes_avg_us": {kind: 1e3 * ms / cnt for kind, (ms, cnt) in prof.items()},
+    }
+
+
 def time_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -390,6 +417,8 @@ def main():
                     help="skip the 64-scene batched-versus-plain-loop measurement")
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the adaptive step-and-threshold measurement")
+    ap.add_argument("--no-rda", action="store_true",
+                    help="skip the range-Doppler operator measurement")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the differentiated (forward + reverse pass) measurement")
     ap.add_argument("--no-profile", action="store_true",
@@ -489,6 +518,10 @@ def main():
     if not args.no_adaptive:
         log("bench: adaptive step and threshold")
         rec["adaptive"] = bench_adaptive(op, y, bits, k, args.iters, 3, dev)
+
+    if not args.no_rda:
+        log("bench: range-Doppler operator")
+        rec["range_doppler"] = bench_rda(shape, y, bits, lam, args.iters, 3, dev)
 
     if not args.no_batched:
         rec["batched"] = bench_batched(3, args.iters, dev)

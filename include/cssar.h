@@ -84,6 +84,29 @@ typedef struct cssar_op cssar_op;
  * device.  *out is set only on success. */
 int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** out);
 
+/* Focusing chains of an operator (cssar_operator_chain). */
+#define CSSAR_CHAIN_CSA 0
+#define CSSAR_CHAIN_RDA 1
+
+/* Build an operator whose M is the range-Doppler algorithm the paper works
+ * as its example (Section III.C, eq. (RDA)) and whose G is built from it by
+ * the inversion rules with D = C^T for the interpolation (eqs. (CD),
+ * (apob)), so G^H = M exactly (Theorem 1) and G is close to M^-1:
+ *     M(Y) = F_eta^-1 [ P_eta o C[ F_tau^-1 [ P_tau o F_tau [ F_eta Y ] ] ] ]
+ *     G(X) = F_tau^-1 [ P_tau* o F_tau [ D[ P_eta* o F_eta X ] ] ], then F_eta^-1
+ *   P_tau = exp(i pi f_tau^2 / Kr); P_eta = exp(-i pi f_eta^2 / Ka(tau_j)),
+ *   Ka = 2 v^2 / (lambda_w R0_j) (no constant phase);
+ *   C (eq. (RCMCs)): U[j] = sum_{t = -K/2+1}^{K/2} V[(p + t) mod N_r] sinc(t - fr),
+ *   p + fr = j + delta_j (p integer, 0 <= fr < 1), delta_j = tau_j (1/D - 1) fs
+ *   range samples, sinc(x) = sin(pi x) / (pi x), K = taps.
+ * taps: even, 2..32 and at most n_rg (CSSAR_EINVAL otherwise).  Every
+ * operator entry point accepts such an operator except the batched and the
+ * gradient ones (CSSAR_EUNSUPPORTED). */
+int cssar_make_operator_rda(const cssar_params* p, int n_az, int n_rg, int taps, cssar_op** out);
+
+/* CSSAR_CHAIN_CSA or CSSAR_CHAIN_RDA; CSSAR_EINVAL for NULL. */
+int cssar_operator_chain(const cssar_op* op);
+
 /* Release an operator and its tables (NULL is accepted). */
 int cssar_destroy_operator(cssar_op* op);
 

@@ -11,12 +11,25 @@ zero fill).  Iteration eq. (th2d) / Algorithm 1:
     dX^(i)  = M(R^(i))                          (matched filter on residue)
     X^(i+1) = E_{1, lambda mu}(X^(i) + mu dX^(i))   (thresholding)
 
-``iters`` counts the updates X^(1) .. X^(iters).
+``iters`` counts the updates X^(1) .. X^(iters).  ``geom`` is an
+oracle.csa.Geometry (chirp-scaling chain) or an oracle.rda.RdaGeometry
+(range-Doppler chain of eq. (RDA)); the iteration is the same.
 """
 
 import numpy as np
 
 from . import csa as _csa
+from . import rda as _rda
+
+
+def _G(x, geom):
+    """G of the focusing chain geom describes (chirp scaling or range-Doppler)."""
+    return _rda.G(x, geom) if isinstance(geom, _rda.RdaGeometry) else _csa.G(x, geom)
+
+
+def _M(y, geom):
+    """M = G^H of the focusing chain geom describes."""
+    return _rda.M(y, geom) if isinstance(geom, _rda.RdaGeometry) else _csa.M(y, geom)
 
 
 def soft_threshold(v, sigma):
@@ -43,11 +56,11 @@ def ita(y, mask, lam, iters, geom, mu=1.0, x0=None):
     hist = []
     for _ in range(int(iters)):
         if np.any(x):
-            r = m * (y - _csa.G(x, geom))
+            r = m * (y - _G(x, geom))
         else:
             r = m * y  # G is linear, so G(0) = 0
         hist.append(float(np.vdot(r, r).real))
-        dx = _csa.M(r, geom)
+        dx = _M(r, geom)
         x = soft_threshold(x + mu * dx, lam * mu)
     return x, hist
 
@@ -56,7 +69,7 @@ def lambda_from_sparsity(y, mask, k, geom, mu=1.0):
     """Section IV.B: lambda = |b_mu(x)|_{k+1} / mu, the (k+1)-th largest
     magnitude of b_mu(x) = x + mu dx, taken once at x = X^(0) = 0, where
     b_mu(0) = mu M(m o y)."""
-    b = mu * _csa.M(np.asarray(mask, dtype=np.float64) * np.asarray(y), geom)
+    b = mu * _M(np.asarray(mask, dtype=np.float64) * np.asarray(y), geom)
     mags = np.sort(np.abs(b).ravel())[::-1]
     return float(mags[int(k)] / mu)
 
@@ -64,7 +77,7 @@ def lambda_from_sparsity(y, mask, k, geom, mu=1.0):
 def objective(x, y, mask, lam, geom):
     """1/2 ||m o (y - G x)||^2 + lambda ||x||_1, the objective whose
     proximal-gradient step with threshold lambda*mu is eq. (th2d)."""
-    r = np.asarray(mask, dtype=np.float64) * (y - _csa.G(x, geom))
+    r = np.asarray(mask, dtype=np.float64) * (y - _G(x, geom))
     return 0.5 * float(np.vdot(r, r).real) + lam * float(np.abs(x).sum())
 
 
@@ -94,7 +107,7 @@ def normalized_step(dx, support, mask, geom):
     num = float(np.vdot(dxk, dxk).real)
     if num == 0.0:
         return 1.0
-    gk = np.asarray(mask, dtype=np.float64) * _csa.G(dxk, geom)
+    gk = np.asarray(mask, dtype=np.float64) * _G(dxk, geom)
     den = float(np.vdot(gk, gk).real)
     return num / den if den > 0.0 else 1.0
 
@@ -116,9 +129,9 @@ def ita_adaptive(y, mask, k, iters, geom, x0=None):
     x = np.zeros_like(y) if x0 is None else np.array(x0, dtype=np.complex128)
     resid, mus, lams = [], [], []
     for _ in range(int(iters)):
-        r = m * (y - _csa.G(x, geom)) if np.any(x) else m * y
+        r = m * (y - _G(x, geom)) if np.any(x) else m * y
         resid.append(float(np.vdot(r, r).real))
-        dx = _csa.M(r, geom)
+        dx = _M(r, geom)
         mu = normalized_step(dx, x != 0, mask, geom)
         v = x + mu * dx
         sigma = kth_largest_magnitude(v, int(k) + 1)

@@ -69,6 +69,26 @@ void build_coefficients(const cssar_params& p, int na, int nr, std::vector<doubl
   }
 }
 
+// Range-Doppler chain (eq. (RDA)) per Doppler bin: the migration in range
+// samples delta_j = a + b j (b = 1/D - 1, a = tau_0 b fs, tau_0 the range
+// time of column 0) and the azimuth filter exp(-i pi f^2 / K_a(tau_j)),
+// K_a = 2 V^2 / (lambda R0), as turns A + B j.
+void build_rda_coefficients(const cssar_params& p, int na, int nr, std::vector<double2>& mig,
+                            std::vector<double2>& az) {
+  const double lam = kC / p.fc;
+  const double tau0 = 2.0 * p.r_ref / kC - 0.5 * nr / p.fs;
+  mig.resize(na);
+  az.resize(na);
+  for (int k = 0; k < na; ++k) {
+    const double f = p.prf * signed_bin(k, na) / na;
+    const double u = lam * f / (2.0 * p.v);
+    const double b = 1.0 / std::sqrt(1.0 - u * u) - 1.0;
+    mig[k] = make_double2(tau0 * b * p.fs, b);
+    const double c = -f * f * lam * kC / (8.0 * p.v * p.v);
+    az[k] = make_double2(c * tau0, c / p.fs);
+  }
+}
+
 void build_twiddles(int n, std::vector<float2>& t) {
   t.resize(n);
   for (int k = 0; k < n; ++k) {
@@ -154,6 +174,9 @@ RowArgs row_args(const cssar_op* op, const void* in, void* out, int conj) {
   a.inv_fs = 1.0 / op->p.fs;
   a.fc_fs = op->p.fc / op->p.fs;
   a.p_c = op->p.fc * 2.0 * op->p.r_ref / kC;
+  const double df = op->p.fs / op->nr;
+  a.c_tau = 0.5 * df * df / op->p.Kr;
+  a.taps = op->taps;
   return a;
 }
 
@@ -169,6 +192,8 @@ hipEvent_t take_event(cssar_op* op) {
 }
 
 int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s) {
+  if (op->chain == CSSAR_CHAIN_RDA)
+    return timed(op, a.conj ? 1 : 0, s, [&] { return op->kr->row_rda[a.conj ? 1 : 0](a, op->grid_row, s); });
   return timed(op, a.conj ? 1 : 0, s, [&] { return op->kr->row(a, op->grid_row, s); });
 }
 
@@ -208,8 +233,14 @@ int cssar_plan_info(int n, int* elems_per_thread, int* n_passes, int* radices) {
 
 const char* cssar_last_error(void) { return g_last_error.c_str(); }
 
-int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** out) {
+}  // extern "C"
+
+namespace cssar {
+namespace detail {
+
+int make_operator_impl(const cssar_params* p, int n_az, int n_rg, int chain, int taps, cssar_op** out) {
   if (!out) return fail(CSSAR_EINVAL, "out is NULL");
+  *out = nullptr;
   int rc = check_params(p);
   if (rc) return rc;
   if (n_az <= 0 || n_rg <= 0) return fail(CSSAR_EINVAL, "grid sizes must be positive");
@@ -220,11 +251,22 @@ int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** ou
   if (n_rg % ka->C != 0 || n_rg % 32 != 0)
     return fail(CSSAR_EUNSUPPORTED, "range length %d incompatible with the column tile", n_rg);
 
+  if (chain == CSSAR_CHAIN_RDA && (taps < 2 || taps > 32 || taps % 2 != 0 || taps > n_rg))
+    return fail(CSSAR_EINVAL, "taps must be even, in 2..32 and at most N_r (got %d)", taps);
   std::vector<double2> r1, r2, r3;
   build_coefficients(*p, n_az, n_rg, r1, r2, r3);
   for (int k = 0; k < n_az; ++k)
     if (!std::isfinite(r1[k].x) || !std::isfinite(r2[k].x) || !std::isfinite(r3[k].y))
       return fail(CSSAR_EINVAL, "parameters give non-finite phase coefficients");
+  if (chain == CSSAR_CHAIN_RDA) {
+    // the range-Doppler tables take the places of Phi1 and Phi3
+    build_rda_coefficients(*p, n_az, n_rg, r1, r3);
+    // a migration beyond the range extent has no meaning on the periodic
+    // grid (and would let the interpolation windows wrap more than once)
+    for (int k = 0; k < n_az; ++k)
+      if (!(std::fabs(r1[k].x) + std::fabs(r1[k].y) * n_rg < 0.5 * n_rg))
+        return fail(CSSAR_EINVAL, "range migration exceeds half the range extent (%d samples)", n_rg);
+  }
   std::vector<float2> ta, tr;
   build_twiddles(n_az, ta);
   build_twiddles(n_rg, tr);
@@ -233,6 +275,8 @@ int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** ou
   op->na = n_az;
   op->nr = n_rg;
   op->p = *p;
+  op->chain = chain;
+  op->taps = chain == CSSAR_CHAIN_RDA ? taps : 0;
   op->ka = ka;
   op->kr = kr;
   auto cleanup = [&](int code) {
@@ -270,7 +314,8 @@ int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** ou
   if (e != hipSuccess) return cleanup(fail(CSSAR_EHIP, "uploading operator tables: %s", hipGetErrorString(e)));
 
   const int row_work = (n_az + kr->LR - 1) / kr->LR;
-  op->grid_row = grid_for(row_work, op->cus, occupancy(kr->row_fn, kr->RT));
+  op->grid_row = grid_for(row_work, op->cus,
+                          occupancy(chain == CSSAR_CHAIN_RDA ? kr->row_rda_fn[0] : kr->row_fn, kr->RT));
   for (int c = 0; c < 2; ++c)
     op->grid_adj[c] = std::min(grid_for(row_work, op->cus, occupancy(kr->row_adj_fn[c], kr->RT)), kMaxPartials / 2);
   for (int w = 0; w < CK_COUNT; ++w) {
@@ -283,6 +328,21 @@ int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** ou
   *out = op;
   return CSSAR_OK;
 }
+
+}  // namespace detail
+}  // namespace cssar
+
+extern "C" {
+
+int cssar_make_operator(const cssar_params* p, int n_az, int n_rg, cssar_op** out) {
+  return make_operator_impl(p, n_az, n_rg, CSSAR_CHAIN_CSA, 0, out);
+}
+
+int cssar_make_operator_rda(const cssar_params* p, int n_az, int n_rg, int taps, cssar_op** out) {
+  return make_operator_impl(p, n_az, n_rg, CSSAR_CHAIN_RDA, taps, out);
+}
+
+int cssar_operator_chain(const cssar_op* op) { return op ? op->chain : CSSAR_EINVAL; }
 
 int cssar_destroy_operator(cssar_op* op) {
   if (!op) return CSSAR_OK;
@@ -375,7 +435,7 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
   float2* X = (float2*)ws;                       // Xt = F_eta X (or Xh) (blocked layout)
   float2* P = (float2*)((char*)ws + blk);        // pass buffer (in place)
   float2* Y = (float2*)((char*)ws + 2 * blk);    // m o y (blocked layout, unsampled marked)
-  constexpr bool scr = CSSAR_SCREENED != 0;
+  const bool scr = CSSAR_SCREENED != 0 && op->chain == CSSAR_CHAIN_CSA;
   auto col = [&](int which, const ColArgs& a) {
     return (scr && which != CK_INV) ? launch_col_scr(op, which, a, s) : launch_col(op, which, a, s);
   };

@@ -332,6 +332,9 @@ int cssar_make_batch(cssar_op* const* ops, int count, cssar_batch** out) {
   if (!ops || count < 1) return fail(CSSAR_EINVAL, "need count >= 1 operators");
   for (int s = 0; s < count; ++s)
     if (!ops[s]) return fail(CSSAR_EINVAL, "operator %d is NULL", s);
+  for (int s = 0; s < count; ++s)
+    if (ops[s]->chain != CSSAR_CHAIN_CSA)
+      return fail(CSSAR_EUNSUPPORTED, "operator %d: batching is built for the chirp-scaling chain only", s);
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   for (int s = 0; s < count; ++s)

@@ -166,6 +166,8 @@ int forward_iteration(cssar_op* op, int t, const float2* Xt, float2* P, float2* 
 int check_solve_args(const cssar_op* op, const void* y, const void* mask, float lambda, int iters, int every) {
   int rc = check_op(op);
   if (rc) return rc;
+  if (op->chain != CSSAR_CHAIN_CSA)
+    return fail(CSSAR_EUNSUPPORTED, "the gradient is built for the chirp-scaling chain only");
   if (!y || !mask) return fail(CSSAR_EINVAL, "NULL array");
   if (iters < 1) return fail(CSSAR_EINVAL, "iters must be >= 1");
   if (every < 1) return fail(CSSAR_EINVAL, "checkpoint interval must be >= 1");

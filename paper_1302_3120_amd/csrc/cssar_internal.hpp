@@ -40,14 +40,16 @@ int grid_for(int work, int cus, int per_cu);
 struct cssar_op {
   int na = 0, nr = 0;
   cssar_params p{};
+  int chain = 0;                    // CSSAR_CHAIN_CSA or CSSAR_CHAIN_RDA
+  int taps = 0;                     // truncated sinc length (range-Doppler chain)
   int device = 0;
   int cus = 0;
   const cssar::KernelTable* ka = nullptr;  // azimuth length N_a (column passes)
   const cssar::KernelTable* kr = nullptr;  // range length N_r (row passes)
   const cssar::KernelTable* kcol[cssar::CK_COUNT] = {};  // per column-pass kind (N_a)
-  double2* rowc1 = nullptr;         // per Doppler bin: Phi1 (a1, d1)
+  double2* rowc1 = nullptr;         // per Doppler bin: Phi1 (a1, d1); range-Doppler: migration (a, b)
   double2* rowc2 = nullptr;         //                  Phi2 (a2, b2)
-  double2* rowc3 = nullptr;         //                  Phi3 (D, b3)
+  double2* rowc3 = nullptr;         //                  Phi3 (D, b3); range-Doppler: azimuth filter (A, B)
   float2* tw_a = nullptr;           // w_{N_a}^k
   float2* tw_r = nullptr;           // w_{N_r}^k
   float* partials = nullptr;        // per-block partial sums

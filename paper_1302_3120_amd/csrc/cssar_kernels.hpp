@@ -84,6 +84,10 @@ struct RowArgs {
                          // polynomials c0 + c1 o + c2 o^2 (radians), ordered
                          // [theta = K_a, K_r][stage 1, 2, 3][c0, c1, c2]
   float* partials;       // per-block partial sums (2 per block)
+  // range-Doppler chain (rowc1: migration (a, b) per Doppler bin, in range
+  // samples delta_j = a + b j; rowc3: azimuth filter turns (A, B), A + B j)
+  double c_tau;          // range filter turns per squared range bin, df^2 / (2 K_r)
+  int taps;              // truncated sinc length K (even)
 };
 
 // Column modes.  FWD, INV, A, R: the forward passes.  VB, U, XB: the
@@ -413,6 +417,143 @@ __global__ __launch_bounds__(P::RT) void row_group_kernel(GroupArgs g) {
     row_unit<P, -1, false, TAB>(args[s], u - g.start[s], ln, lds, twl, hp, qt);
     par ^= 1;
   }
+}
+
+// ------------------------------------------------- range-Doppler row pass --
+// The row (range) part of the range-Doppler chain of eq. (RDA), one Doppler
+// bin per line, the azimuth transforms being the column passes':
+//   M:  F_tau -> x P_tau / N_r -> F_tau^-1 -> C (migration) -> x P_eta
+//   G:  x P_eta* -> D = C^T -> F_tau -> x P_tau* / N_r -> F_tau^-1
+// C (eq. (RCMCs)): U[j] = sum_t V[(p + t) mod N] sinc(t - fr), t = -K/2+1 ..
+// K/2, p + fr = j + delta_j (p integer, 0 <= fr < 1), delta_j = a + b j.
+// D (eq. (CD)) gathers the same pairs from the output side: V[l] = sum over
+// the j whose window holds l (l = p_j + t modulo N) of U[j] sinc(x),
+// x = L - j - delta_j in (-K/2, K/2] for the unwrapped L = l + m N.  The
+// line goes through LDS for the gather.
+
+// sinc(x) = sin(pi x) / (pi x): a Taylor polynomial in (pi x)^2 for |x| < 1/2
+// (error < 4e-8), else the hardware sine of the reduced half-turn.
+__device__ __forceinline__ float sinc_small(float x) {
+  const float z = 9.8696044f * x * x;  // (pi x)^2
+  return fmaf(z, fmaf(z, fmaf(z, fmaf(z, fmaf(z, -2.5052108e-8f, 2.7557319e-6f), -1.9841270e-4f),
+                                8.3333333e-3f), -1.6666667e-1f), 1.0f);
+}
+__device__ __forceinline__ float sinc_f(float x) {
+  if (fabsf(x) < 0.5f) return sinc_small(x);
+  const float h = 0.5f * x;
+  return __builtin_amdgcn_sinf(h - rintf(h)) / (3.14159265f * x);
+}
+
+template <class P, int CONJ>
+__device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const RowLane<P>& ln, float2* lds,
+                                             const float2* twl, const TwPowers& hp) {
+  constexpr int HS = hoisted_pass<P>();
+  constexpr int N = P::N, E = P::E, T = P::T, LR = P::LR;
+  constexpr int LI = RowLds<P>::LI, LS = RowLds<P>::LS;
+  const uint32_t S = b4_stride(N);
+  const uint32_t bytes = clamp_bytes(b4_bytes(a.na, N));
+  const Buf in(a.in, bytes), out(a.out, bytes);
+  constexpr bool cj = CONJ != 0;
+  const int b = ln.b, line = ln.line;
+  const int row = gi * LR + line;
+  const uint32_t vo = (uint32_t)(row >> 2) * S + (uint32_t)(b >> 2) * 128u + (uint32_t)(row & 3) * 32u +
+                      (uint32_t)(b & 3) * 8u;
+  float2 v[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) v[k] = in.f2(vo, T * k * 32);
+  const double2 mig = a.rowc1[row], az = a.rowc3[row];
+  int lb = b, lc = line % LI;
+  asm volatile("" : "+v"(lb), "+v"(lc));
+  int loff = (line / LI) * LS;
+  asm volatile("" : "+v"(loff));
+  float2* ll = lds + loff;  // this line's LDS (interleaved with the unit's other lines)
+  const TwLds tws{twl, twl + 64};
+  const Quad q_eta = quad_in_slot(fma(az.y, 0.5 * N, az.x), az.y, 0.0, b, T);
+  const int K = a.taps;
+  // line through LDS (the exchanges of fft_line leave the LDS free)
+  auto stage = [&]() {
+#pragma unroll
+    for (int k = 0; k < E; ++k) ll[lds_pad<LI>((unsigned)((b + T * k) * LI + lc))] = v[k];
+    __syncthreads();
+  };
+  auto at = [&](int j) { return ll[lds_pad<LI>((unsigned)(j * LI + lc))]; };
+  if constexpr (cj) {
+    apply_quad<E, false>(v, q_eta, true, 1.0f);
+    // D: gather over the windows that hold each output
+    stage();
+    const double a0 = mig.x, b1 = 1.0 + mig.y;
+    const double pmin = floor(a0) - K / 2 + 1, pmax = floor(a0 + b1 * (N - 1)) + K / 2;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int l = b + T * k;
+      float2 acc = make_float2(0.f, 0.f);
+      const int m_lo = (int)ceil((pmin - l) / N), m_hi = (int)floor((pmax - l) / N);
+      for (int m = m_lo; m <= m_hi; ++m) {
+        const double L = (double)l + (double)m * N;
+        int j0 = (int)ceil((L - a0 - 0.5 * K) / b1), j1 = (int)ceil((L - a0 + 0.5 * K) / b1) - 1;
+        j0 = max(j0, 0);
+        j1 = min(j1, N - 1);
+        for (int j = j0; j <= j1; ++j) {
+          const float x = (float)(L - a0 - b1 * j);
+          const float w = sinc_f(x);
+          const float2 u = at(j);
+          acc = make_float2(fmaf(w, u.x, acc.x), fmaf(w, u.y, acc.y));
+        }
+      }
+      v[k] = acc;
+    }
+    __syncthreads();
+    fft_line<P, false, LI, TwLds, 0, HS>(v, lb, lc, ll, tws, hp);
+    apply_quad<E, true>(v, quad_in_slot(0.0, 0.0, a.c_tau, b, T), true, a.scale);
+    asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
+    fft_line<P, true, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
+  } else {
+    fft_line<P, false, LI, TwLds, 0, HS>(v, lb, lc, ll, tws, hp);
+    apply_quad<E, true>(v, quad_in_slot(0.0, 0.0, a.c_tau, b, T), false, a.scale);
+    asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
+    fft_line<P, true, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
+    // C: gather the K taps of each output's window
+    stage();
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int j = b + T * k;
+      const double pos = fma(mig.y, (double)j, mig.x) + (double)j;
+      const double pf = floor(pos);
+      const float fr = (float)(pos - pf);
+      // sin(pi (t - fr)) = (-1)^(t+1) sin(pi fr) for integer t
+      const float s = __builtin_amdgcn_sinf(0.5f * fr);
+      int q = (int)(((long long)pf - K / 2 + 1) % N);
+      if (q < 0) q += N;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int t = -K / 2 + 1; t <= K / 2; ++t) {
+        const float x = (float)t - fr;
+        const float w = fabsf(x) < 0.5f ? sinc_small(x) : ((t & 1) ? s : -s) / (3.14159265f * x);
+        const float2 u = at(q);
+        acc = make_float2(fmaf(w, u.x, acc.x), fmaf(w, u.y, acc.y));
+        if (++q == N) q = 0;
+      }
+      v[k] = acc;
+    }
+    __syncthreads();
+    apply_quad<E, false>(v, q_eta, false, 1.0f);
+  }
+#pragma unroll
+  for (int k = 0; k < E; ++k) out.st(v[k], vo, T * k * 32);
+}
+
+template <class P, int CONJ>
+__global__ __launch_bounds__(P::RT) void row_rda_kernel(RowArgs a) {
+  __shared__ float2 lds[RowLds<P>::size];
+  __shared__ float2 twl[64 + P::N / 64];
+  load_twiddle_table<P::N>(twl, a.tw);
+  __syncthreads();
+  const RowLane<P> ln;
+  TwPowers hp;
+  if constexpr (hoisted_pass<P>() >= 0)
+    hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(ln.b, TwLds{twl, twl + 64});
+  const int units = a.na / P::LR;
+  for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x)
+    row_rda_unit<P, CONJ>(a, gi, ln, lds, twl, hp);
 }
 
 // ------------------------------------------------------ adjoint row pass --
@@ -917,6 +1058,11 @@ struct Kernels {
   }
   static hipError_t row_group(const GroupArgs& g, int grid, hipStream_t s) {
     hipLaunchKernelGGL(row_group_kernel<P>, dim3(grid), dim3(P::RT), 0, s, g);
+    return hipGetLastError();
+  }
+  template <int CONJ>
+  static hipError_t row_rda(const RowArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((row_rda_kernel<P, CONJ>), dim3(grid), dim3(P::RT), 0, s, a);
     return hipGetLastError();
   }
   template <int CONJ>

@@ -32,6 +32,7 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
       &K::row_mid,
       {&K::template col_scr<COL_FWD>, &K::template col<COL_INV>, &K::template col_scr<COL_A>,
        &K::template col_scr<COL_R>},
+      {&K::template row_rda<0>, &K::template row_rda<1>},
       reinterpret_cast<const void*>(&row_pass_kernel<P, 0, false>),
       {reinterpret_cast<const void*>(&col_pass_kernel<P, COL_FWD, false>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_INV, false>),
@@ -56,6 +57,8 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_INV, false>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_A, true>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_R, true>)},
+      {reinterpret_cast<const void*>(&row_rda_kernel<P, 0>),
+       reinterpret_cast<const void*>(&row_rda_kernel<P, 1>)},
   };
   return &t;
 }

@@ -28,6 +28,7 @@ SYMBOLS = (
     "cssar_batch_set_graph", "cssar_batch_autotune", "cssar_batch_describe",
     "cssar_ita_solve_batched", "cssar_checkpoint_size", "cssar_grad_workspace_size",
     "cssar_ita_forward", "cssar_ita_backward", "cssar_ita_solve_adaptive",
+    "cssar_make_operator_rda", "cssar_operator_chain",
 )
 
 PROFILE_KINDS = ("row_M", "row_G", "col_fwd", "col_inv", "col_update_threshold",
@@ -72,6 +73,10 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, i, f = ctypes.c_void_p, ctypes.c_int, ctypes.c_float
         L.cssar_make_operator.argtypes = [ctypes.POINTER(Params), i, i, ctypes.POINTER(vp)]
+        L.cssar_make_operator_rda.argtypes = [ctypes.POINTER(Params), i, i, i, ctypes.POINTER(vp)]
+        L.cssar_make_operator_rda.restype = ctypes.c_int
+        L.cssar_operator_chain.argtypes = [vp]
+        L.cssar_operator_chain.restype = ctypes.c_int
         L.cssar_destroy_operator.argtypes = [vp]
         L.cssar_workspace_size.argtypes = [vp, i]
         L.cssar_workspace_size.restype = ctypes.c_size_t
@@ -143,17 +148,28 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+CHAINS = ("csa", "rda")
+
+
 class Operator:
     """Approximated observation G and its adjoint G^H = M on an
-    N_a x N_r grid (the handle of cssar_make_operator)."""
+    N_a x N_r grid (the handle of cssar_make_operator, or of
+    cssar_make_operator_rda with chain="rda" and a truncated-sinc length taps)."""
 
-    def __init__(self, params, shape):
+    def __init__(self, params, shape, chain="csa", taps=8):
+        if chain not in CHAINS:
+            raise ValueError(f"chain must be one of {CHAINS}")
         self.shape = (int(shape[0]), int(shape[1]))
         self.params = dict(params)
+        self.chain = chain
         self._p = Params.from_dict(params)
         h = ctypes.c_void_p()
-        _check(lib().cssar_make_operator(ctypes.byref(self._p), self.shape[0],
-                                         self.shape[1], ctypes.byref(h)))
+        if chain == "csa":
+            _check(lib().cssar_make_operator(ctypes.byref(self._p), self.shape[0],
+                                             self.shape[1], ctypes.byref(h)))
+        else:
+            _check(lib().cssar_make_operator_rda(ctypes.byref(self._p), self.shape[0],
+                                                 self.shape[1], int(taps), ctypes.byref(h)))
         self._h = h
 
     def close(self):
@@ -298,8 +314,8 @@ class Operator:
         return {PROFILE_KINDS[k]: (ms[k], cnt[k]) for k in range(NK) if cnt[k]}
 
 
-def make_operator(params, shape):
-    return Operator(params, shape)
+def make_operator(params, shape, chain="csa", taps=8):
+    return Operator(params, shape, chain, taps)
 
 
 def _ptrs(ts):

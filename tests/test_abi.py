@@ -87,6 +87,14 @@ def test_make_operator_rejects_before_any_hip_call(L, kw, shape, code):
     assert len(L.cssar_last_error()) > 0
 
 
+@pytest.mark.parametrize("taps", [0, 3, 34, -2])
+def test_make_operator_rda_rejects_taps_before_any_hip_call(L, taps):
+    p = _params()
+    h = ctypes.c_void_p()
+    assert L.cssar_make_operator_rda(ctypes.byref(p), 256, 256, taps, ctypes.byref(h)) == -1
+    assert h.value is None
+
+
 def test_null_arguments(L):
     h = ctypes.c_void_p()
     assert L.cssar_make_operator(None, 256, 256, ctypes.byref(h)) == -1
@@ -98,6 +106,9 @@ def test_null_arguments(L):
     assert L.cssar_ita_solve_adaptive(None, None, None, 10, 10, None, None, None, None, None,
                                       None) == -1
     assert L.cssar_workspace_size(None, 2) == 0
+    assert L.cssar_make_operator_rda(None, 256, 256, 8, ctypes.byref(h)) == -1
+    assert L.cssar_make_operator_rda(ctypes.byref(p), 256, 256, 8, None) == -1
+    assert L.cssar_operator_chain(None) == -1
     assert L.cssar_pack_mask(None, None, None, None) == -1
     assert L.cssar_sync_status(None, None) == -1
     assert L.cssar_destroy_operator(None) == 0

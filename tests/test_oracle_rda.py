@@ -170,3 +170,20 @@ def test_G_inverts_M_up_to_the_interpolation_error():
         rg = rda.RdaGeometry(STRIP, shape, taps)
         errs.append(np.linalg.norm(rda.G(rda.M(y, rg), rg) - y) / np.linalg.norm(y))
     assert errs[0] <= 0.15 and errs[1] < errs[0]
+
+
+def test_iteration_runs_on_the_range_doppler_chain():
+    # The solver oracle takes either chain: on y = m o G(x*) built with the
+    # range-Doppler G, the adaptive iteration recovers x* itself (the
+    # iteration only needs G and its adjoint M), and X(1) = S(M(m o y)).
+    from oracle import ita
+    shape = (32, 32)
+    rg = rda.RdaGeometry(STRIP, shape)
+    rows, cols, sig = inputs.point_targets(shape, 4, seed=3)
+    xt = inputs.targets_to_image(shape, rows, cols, sig)
+    mask = inputs.random_mask(shape, 0.6, seed=4)
+    y = mask * rda.G(xt, rg)
+    x1, _ = ita.ita(y, mask, 0.3, 1, rg)
+    assert np.abs(x1 - ita.soft_threshold(rda.M(y, rg), 0.3)).max() <= 1e-12
+    x, *_ = ita.ita_adaptive(y, mask, 4, 80, rg)
+    assert np.linalg.norm(x - xt) <= 1e-8 * np.linalg.norm(xt)
