@@ -431,17 +431,12 @@ __global__ __launch_bounds__(P::RT) void row_group_kernel(GroupArgs g) {
 // x = L - j - delta_j in (-K/2, K/2] for the unwrapped L = l + m N.  The
 // line goes through LDS for the gather.
 
-// sinc(x) = sin(pi x) / (pi x): a Taylor polynomial in (pi x)^2 for |x| < 1/2
-// (error < 4e-8), else the hardware sine of the reduced half-turn.
+// sinc(x) = sin(pi x) / (pi x) for |x| <= 1/2: Taylor polynomial in (pi x)^2
+// (error < 4e-8).
 __device__ __forceinline__ float sinc_small(float x) {
   const float z = 9.8696044f * x * x;  // (pi x)^2
   return fmaf(z, fmaf(z, fmaf(z, fmaf(z, fmaf(z, -2.5052108e-8f, 2.7557319e-6f), -1.9841270e-4f),
                                 8.3333333e-3f), -1.6666667e-1f), 1.0f);
-}
-__device__ __forceinline__ float sinc_f(float x) {
-  if (fabsf(x) < 0.5f) return sinc_small(x);
-  const float h = 0.5f * x;
-  return __builtin_amdgcn_sinf(h - rintf(h)) / (3.14159265f * x);
 }
 
 template <class P, int CONJ>
@@ -461,14 +456,17 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
   float2 v[E];
 #pragma unroll
   for (int k = 0; k < E; ++k) v[k] = in.f2(vo, T * k * 32);
-  const double2 mig = a.rowc1[row], az = a.rowc3[row];
   int lb = b, lc = line % LI;
   asm volatile("" : "+v"(lb), "+v"(lc));
   int loff = (line / LI) * LS;
   asm volatile("" : "+v"(loff));
   float2* ll = lds + loff;  // this line's LDS (interleaved with the unit's other lines)
   const TwLds tws{twl, twl + 64};
-  const Quad q_eta = quad_in_slot(fma(az.y, 0.5 * N, az.x), az.y, 0.0, b, T);
+  // azimuth filter turns A + B j = (A + B N/2) + B o, o = j - N/2
+  auto q_eta = [&]() {
+    const double2 az = a.rowc3[row];
+    return quad_in_slot(fma(az.y, 0.5 * N, az.x), az.y, 0.0, b, T);
+  };
   const int K = a.taps;
   // line through LDS (the exchanges of fft_line leave the LDS free)
   auto stage = [&]() {
@@ -476,31 +474,52 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
     for (int k = 0; k < E; ++k) ll[lds_pad<LI>((unsigned)((b + T * k) * LI + lc))] = v[k];
     __syncthreads();
   };
-  auto at = [&](int j) { return ll[lds_pad<LI>((unsigned)(j * LI + lc))]; };
+  // element j of this line: lds_pad<LI>(j LI + lc) = LI (j + j / 16) + lc
+  auto at = [&](int j) { return ll[LI * (j + (j >> 4)) + lc]; };
   if constexpr (cj) {
-    apply_quad<E, false>(v, q_eta, true, 1.0f);
-    // D: gather over the windows that hold each output
+    apply_quad<E, false>(v, q_eta(), true, 1.0f);
+    // D: for output l and an unwrapped position L = l + m N, the inputs j
+    // with x_j = L - a - (1 + b) j in (-K/2, K/2] are consecutive; along them
+    // x falls by 1 + b, so sin(pi x_c) = (-1)^c sin(pi (x_0 - c b)) follows
+    // by rotating (sin, cos) by -pi b, and only the candidate nearest x = 0
+    // takes the polynomial.
     stage();
-    const double a0 = mig.x, b1 = 1.0 + mig.y;
-    const double pmin = floor(a0) - K / 2 + 1, pmax = floor(a0 + b1 * (N - 1)) + K / 2;
+    const double2 mig = a.rowc1[row];
+    const double a0 = mig.x, b1 = 1.0 + mig.y, inv_b1 = 1.0 / b1;
+    const float b1f = (float)b1, bf = (float)mig.y;
+    const float2 rot = cis_turns(-0.5 * mig.y);  // (cos, sin) of -pi b
+    // windows span the unwrapped positions pmin .. pmax
+    const int pmin = (int)floor(a0) - K / 2 + 1, pmax = (int)floor(fma(b1, (double)(N - 1), a0)) + K / 2;
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const int l = b + T * k;
       float2 acc = make_float2(0.f, 0.f);
-      const int m_lo = (int)ceil((pmin - l) / N), m_hi = (int)floor((pmax - l) / N);
+      const int m_lo = (pmin - l + 4 * N + N - 1) / N - 4, m_hi = (pmax - l + 4 * N) / N - 4;
       for (int m = m_lo; m <= m_hi; ++m) {
-        const double L = (double)l + (double)m * N;
-        int j0 = (int)ceil((L - a0 - 0.5 * K) / b1), j1 = (int)ceil((L - a0 + 0.5 * K) / b1) - 1;
-        j0 = max(j0, 0);
-        j1 = min(j1, N - 1);
-        for (int j = j0; j <= j1; ++j) {
-          const float x = (float)(L - a0 - b1 * j);
-          const float w = sinc_f(x);
+        const double xl = (double)(l + m * N) - a0;
+        const int j0 = max((int)ceil((xl - 0.5 * K) * inv_b1), 0);
+        const int j1 = min((int)ceil((xl + 0.5 * K) * inv_b1) - 1, N - 1);
+        if (j0 > j1) continue;
+        const float x0 = (float)fma(-b1, (double)j0, xl);
+        const float2 cs0 = cis_turns(0.5 * (double)x0);  // (cos, sin) of pi x0
+        float sn = cs0.y, cn = cs0.x;
+        const int cnear = (int)rintf(x0 / b1f);
+        const float xn = fmaf(-(float)cnear, b1f, x0);
+        const float wnear = sinc_small(xn);
+        for (int j = j0, c = 0; j <= j1; ++j, ++c) {
+          const float x = fmaf(-(float)c, bf, x0 - (float)c);
+          const float sx = (c & 1) ? -sn : sn;
+          float w = sx * __builtin_amdgcn_rcpf(3.14159265f * x);
+          if (c == cnear && fabsf(xn) < 0.5f) w = wnear;
           const float2 u = at(j);
           acc = make_float2(fmaf(w, u.x, acc.x), fmaf(w, u.y, acc.y));
+          const float sn2 = fmaf(sn, rot.x, cn * rot.y);  // sin(theta - pi b)
+          cn = fmaf(cn, rot.x, -sn * rot.y);               // cos(theta - pi b)
+          sn = sn2;
         }
       }
       v[k] = acc;
+      __builtin_amdgcn_sched_barrier(0);  // one output at a time (register pressure)
     }
     __syncthreads();
     fft_line<P, false, LI, TwLds, 0, HS>(v, lb, lc, ll, tws, hp);
@@ -512,30 +531,36 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
     apply_quad<E, true>(v, quad_in_slot(0.0, 0.0, a.c_tau, b, T), false, a.scale);
     asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
     fft_line<P, true, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
-    // C: gather the K taps of each output's window
+    // C: the K taps of each output's window; sin(pi (t - fr)) =
+    // (-1)^(t+1) sin(pi fr), and the tap nearest the position takes the
+    // polynomial
     stage();
+    const double2 mig = a.rowc1[row];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const int j = b + T * k;
       const double pos = fma(mig.y, (double)j, mig.x) + (double)j;
       const double pf = floor(pos);
       const float fr = (float)(pos - pf);
-      // sin(pi (t - fr)) = (-1)^(t+1) sin(pi fr) for integer t
-      const float s = __builtin_amdgcn_sinf(0.5f * fr);
-      int q = (int)(((long long)pf - K / 2 + 1) % N);
-      if (q < 0) q += N;
+      const float sp = __builtin_amdgcn_sinf(0.5f * fr) * 0.31830989f;  // sin(pi fr) / pi
+      const int tn = fr < 0.5f ? 0 : 1;
+      const float wnear = sinc_small(fr < 0.5f ? fr : 1.0f - fr);
+      // |delta| < N/2 (checked on the host), so the window start is > -2N
+      int q = ((int)pf - K / 2 + 1 + 2 * N) % N;
       float2 acc = make_float2(0.f, 0.f);
+#pragma unroll 2
       for (int t = -K / 2 + 1; t <= K / 2; ++t) {
-        const float x = (float)t - fr;
-        const float w = fabsf(x) < 0.5f ? sinc_small(x) : ((t & 1) ? s : -s) / (3.14159265f * x);
+        float w = ((t & 1) ? sp : -sp) * __builtin_amdgcn_rcpf((float)t - fr);
+        if (t == tn) w = wnear;
         const float2 u = at(q);
         acc = make_float2(fmaf(w, u.x, acc.x), fmaf(w, u.y, acc.y));
         if (++q == N) q = 0;
       }
       v[k] = acc;
+      __builtin_amdgcn_sched_barrier(0);  // one output at a time (register pressure)
     }
     __syncthreads();
-    apply_quad<E, false>(v, q_eta, false, 1.0f);
+    apply_quad<E, false>(v, q_eta(), false, 1.0f);
   }
 #pragma unroll
   for (int k = 0; k < E; ++k) out.st(v[k], vo, T * k * 32);
