@@ -439,12 +439,18 @@ __device__ __forceinline__ float sinc_small(float x) {
                                 8.3333333e-3f), -1.6666667e-1f), 1.0f);
 }
 
-template <class P, int CONJ>
+// KT: the tap count at compile time (its loops unrolled, the line staged in
+// LDS without padding so every tap is an immediate offset, plus a copy of
+// the line's first KT - 1 elements after its end where it fits, so a window
+// never wraps), or 0 for any even count read from a.taps.
+template <class P, int CONJ, int KT>
 __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const RowLane<P>& ln, float2* lds,
                                              const float2* twl, const TwPowers& hp) {
   constexpr int HS = hoisted_pass<P>();
   constexpr int N = P::N, E = P::E, T = P::T, LR = P::LR;
   constexpr int LI = RowLds<P>::LI, LS = RowLds<P>::LS;
+  constexpr bool FIX = KT > 0;
+  constexpr bool HALO = FIX && LS >= LI * (N + KT);  // room for the wrap copy and over-reads
   const uint32_t S = b4_stride(N);
   const uint32_t bytes = clamp_bytes(b4_bytes(a.na, N));
   const Buf in(a.in, bytes), out(a.out, bytes);
@@ -467,26 +473,33 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
     const double2 az = a.rowc3[row];
     return quad_in_slot(fma(az.y, 0.5 * N, az.x), az.y, 0.0, b, T);
   };
-  const int K = a.taps;
+  const int K = FIX ? KT : a.taps;
+  // element j of this line in LDS: unpadded with a fixed tap count (reads of
+  // consecutive j by the lanes of a wave are still conflict-free), else the
+  // exchanges' padded order lds_pad<LI>(j LI + lc) = LI (j + j / 16) + lc
+  auto idx = [&](int j) { return FIX ? LI * j + lc : LI * (j + (j >> 4)) + lc; };
+  auto at = [&](int j) { return ll[idx(j)]; };
   // line through LDS (the exchanges of fft_line leave the LDS free)
-  auto stage = [&]() {
+  auto stage = [&](bool halo) {
 #pragma unroll
-    for (int k = 0; k < E; ++k) ll[lds_pad<LI>((unsigned)((b + T * k) * LI + lc))] = v[k];
+    for (int k = 0; k < E; ++k) {
+      const int j = b + T * k;
+      ll[idx(j)] = v[k];
+      if (halo && j < K - 1) ll[idx(N + j)] = v[k];
+    }
     __syncthreads();
   };
-  // element j of this line: lds_pad<LI>(j LI + lc) = LI (j + j / 16) + lc
-  auto at = [&](int j) { return ll[LI * (j + (j >> 4)) + lc]; };
   if constexpr (cj) {
     apply_quad<E, false>(v, q_eta(), true, 1.0f);
     // D: for output l and an unwrapped position L = l + m N, the inputs j
-    // with x_j = L - a - (1 + b) j in (-K/2, K/2] are consecutive; along them
-    // x falls by 1 + b, so sin(pi x_c) = (-1)^c sin(pi (x_0 - c b)) follows
-    // by rotating (sin, cos) by -pi b, and only the candidate nearest x = 0
-    // takes the polynomial.
-    stage();
+    // with x_j = L - a - (1 + b) j in (-K/2, K/2] are consecutive (at most K
+    // of them); along them x falls by 1 + b, so sin(pi x_c) =
+    // (-1)^c sin(pi (x_0 - c b)) follows by rotating (sin, cos) by -pi b, and
+    // only the candidate nearest x = 0 takes the polynomial.
+    stage(false);
     const double2 mig = a.rowc1[row];
     const double a0 = mig.x, b1 = 1.0 + mig.y, inv_b1 = 1.0 / b1;
-    const float b1f = (float)b1, bf = (float)mig.y;
+    const float b1f = (float)b1, bf = (float)mig.y, inv_b1f = (float)inv_b1;
     const float2 rot = cis_turns(-0.5 * mig.y);  // (cos, sin) of -pi b
     // windows span the unwrapped positions pmin .. pmax
     const int pmin = (int)floor(a0) - K / 2 + 1, pmax = (int)floor(fma(b1, (double)(N - 1), a0)) + K / 2;
@@ -503,19 +516,29 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
         const float x0 = (float)fma(-b1, (double)j0, xl);
         const float2 cs0 = cis_turns(0.5 * (double)x0);  // (cos, sin) of pi x0
         float sn = cs0.y, cn = cs0.x;
-        const int cnear = (int)rintf(x0 / b1f);
+        int cnear = (int)rintf(x0 * inv_b1f);
         const float xn = fmaf(-(float)cnear, b1f, x0);
         const float wnear = sinc_small(xn);
-        for (int j = j0, c = 0; j <= j1; ++j, ++c) {
+        if (!(fabsf(xn) < 0.5f)) cnear = -1;  // no candidate within 1/2 of x = 0
+        const int cnt = j1 - j0;  // candidates c = 0 .. cnt
+        const float2* base = ll + idx(j0);
+        auto cand = [&](int c) {
           const float x = fmaf(-(float)c, bf, x0 - (float)c);
           const float sx = (c & 1) ? -sn : sn;
           float w = sx * __builtin_amdgcn_rcpf(3.14159265f * x);
-          if (c == cnear && fabsf(xn) < 0.5f) w = wnear;
-          const float2 u = at(j);
+          if (c == cnear) w = wnear;
+          const float2 u = FIX ? base[c * LI] : at(j0 + c);  // (the padded order is not linear)
           acc = make_float2(fmaf(w, u.x, acc.x), fmaf(w, u.y, acc.y));
           const float sn2 = fmaf(sn, rot.x, cn * rot.y);  // sin(theta - pi b)
           cn = fmaf(cn, rot.x, -sn * rot.y);               // cos(theta - pi b)
           sn = sn2;
+        };
+        if constexpr (FIX) {
+#pragma unroll
+          for (int c = 0; c < KT; ++c)
+            if (c <= cnt) cand(c);
+        } else {
+          for (int c = 0; c <= cnt; ++c) cand(c);
         }
       }
       v[k] = acc;
@@ -534,7 +557,7 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
     // C: the K taps of each output's window; sin(pi (t - fr)) =
     // (-1)^(t+1) sin(pi fr), and the tap nearest the position takes the
     // polynomial
-    stage();
+    stage(HALO);
     const double2 mig = a.rowc1[row];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
@@ -548,13 +571,21 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
       // |delta| < N/2 (checked on the host), so the window start is > -2N
       int q = ((int)pf - K / 2 + 1 + 2 * N) % N;
       float2 acc = make_float2(0.f, 0.f);
-#pragma unroll 2
-      for (int t = -K / 2 + 1; t <= K / 2; ++t) {
+      auto tap = [&](int t, float2 u) {
         float w = ((t & 1) ? sp : -sp) * __builtin_amdgcn_rcpf((float)t - fr);
         if (t == tn) w = wnear;
-        const float2 u = at(q);
         acc = make_float2(fmaf(w, u.x, acc.x), fmaf(w, u.y, acc.y));
-        if (++q == N) q = 0;
+      };
+      if constexpr (HALO) {
+        const float2* base = ll + idx(q);  // q + KT - 1 < N + KT - 1: inside the copy
+#pragma unroll
+        for (int i = 0; i < KT; ++i) tap(i - KT / 2 + 1, base[i * LI]);
+      } else {
+#pragma unroll 2
+        for (int t = -K / 2 + 1; t <= K / 2; ++t) {
+          tap(t, at(q));
+          if (++q == N) q = 0;
+        }
       }
       v[k] = acc;
       __builtin_amdgcn_sched_barrier(0);  // one output at a time (register pressure)
@@ -566,7 +597,7 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
   for (int k = 0; k < E; ++k) out.st(v[k], vo, T * k * 32);
 }
 
-template <class P, int CONJ>
+template <class P, int CONJ, int KT>
 __global__ __launch_bounds__(P::RT) void row_rda_kernel(RowArgs a) {
   __shared__ float2 lds[RowLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
@@ -578,7 +609,7 @@ __global__ __launch_bounds__(P::RT) void row_rda_kernel(RowArgs a) {
     hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(ln.b, TwLds{twl, twl + 64});
   const int units = a.na / P::LR;
   for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x)
-    row_rda_unit<P, CONJ>(a, gi, ln, lds, twl, hp);
+    row_rda_unit<P, CONJ, KT>(a, gi, ln, lds, twl, hp);
 }
 
 // ------------------------------------------------------ adjoint row pass --
@@ -1085,9 +1116,13 @@ struct Kernels {
     hipLaunchKernelGGL(row_group_kernel<P>, dim3(grid), dim3(P::RT), 0, s, g);
     return hipGetLastError();
   }
+  // range-Doppler row pass: 8 taps (the default) unrolled, other counts generic
   template <int CONJ>
   static hipError_t row_rda(const RowArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((row_rda_kernel<P, CONJ>), dim3(grid), dim3(P::RT), 0, s, a);
+    if (a.taps == 8)
+      hipLaunchKernelGGL((row_rda_kernel<P, CONJ, 8>), dim3(grid), dim3(P::RT), 0, s, a);
+    else
+      hipLaunchKernelGGL((row_rda_kernel<P, CONJ, 0>), dim3(grid), dim3(P::RT), 0, s, a);
     return hipGetLastError();
   }
   template <int CONJ>

@@ -57,8 +57,8 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_INV, false>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_A, true>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_R, true>)},
-      {reinterpret_cast<const void*>(&row_rda_kernel<P, 0>),
-       reinterpret_cast<const void*>(&row_rda_kernel<P, 1>)},
+      {reinterpret_cast<const void*>(&row_rda_kernel<P, 0, 8>),
+       reinterpret_cast<const void*>(&row_rda_kernel<P, 1, 8>)},
   };
   return &t;
 }
