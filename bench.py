@@ -34,15 +34,21 @@ PASS_BYTES = {
 # Per pixel per ITA iteration (row G, col R, row M, col A: 80 B) plus the
 # mask (1/8 B): the conventional figure for the fraction of HBM peak.
 ITER_BYTES = 80.125
-# Kernel symbol of each pass kind (row_M and row_G share one kernel).
+# Kernel symbol of each pass kind; {v} is the plan variant (the residual
+# column pass at 4096 runs variant 1, see column_variant in cssar_api.hip).
 KIND_SYMBOL = {
     "row_M": "row_pass_kernel<cssar::Plan<{n}, 0>, 0, false>",
     "row_G": "row_pass_kernel<cssar::Plan<{n}, 0>, 1, false>",
     "col_fwd": "col_pass_kernel<cssar::Plan<{n}, 0>, 0, false>",
     "col_inv": "col_pass_kernel<cssar::Plan<{n}, 0>, 1, false>",
     "col_update_threshold": "col_pass_kernel<cssar::Plan<{n}, 0>, 2, false>",
-    "col_residual": "col_pass_kernel<cssar::Plan<{n}, 0>, 3, false>",
+    "col_residual": "col_pass_kernel<cssar::Plan<{n}, {v}>, 3, false>",
 }
+
+
+def kind_symbol(kind, n):
+    """Kernel symbol of a pass kind at line length n."""
+    return KIND_SYMBOL[kind].format(n=n, v=1 if (kind == "col_residual" and n == 4096) else 0)
 # Counter-based HBM bytes per dispatch, written by --rocprof-summary from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and a copy-kernel calibration.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ita_passes_sparse_4096.md")
@@ -319,11 +325,12 @@ def _rows(pattern):
     return out
 
 
-def rocprof_summary(stats_dir, fetch_dir, write_dir, n, command):
+def rocprof_summary(stats_dir, fetch_dir, write_dir, n, command, title="ITA passes"):
     """Text summary of rocprofv3 output: per-kernel durations (kernel-trace
     --stats) and per-dispatch HBM bytes (FETCH_SIZE and WRITE_SIZE runs, each
-    scaled so that the calibration copy reads and writes CAL_MIB MiB)."""
-    lines = ["# rocprofv3 summary: ITA passes at %dx%d complex64" % (n, n), "",
+    scaled so that the calibration copy reads and writes CAL_MIB MiB).  With
+    fetch_dir "-" only the durations (all kernels)."""
+    lines = ["# rocprofv3 summary: %s at %dx%d complex64" % (title, n, n), "",
              "Commands (from the repository root, on one MI355X):", ""]
     lines += ["    " + c for c in command]
     lines += ["", "## Kernel durations (--kernel-trace --stats)", "",
@@ -331,11 +338,15 @@ def rocprof_summary(stats_dir, fetch_dir, write_dir, n, command):
               "|---|---|---|---|---|---|"]
     stats = sorted(_rows(os.path.join(stats_dir, "**", "*kernel_stats.csv")),
                    key=lambda r: -float(r["Percentage"]))
-    for r in stats[:8]:
+    for r in stats[:8] if fetch_dir != "-" else stats:
+        if fetch_dir == "-" and float(r["Percentage"]) < 0.05:
+            continue
         name = r["Name"] if len(r["Name"]) <= 90 else r["Name"][:87] + "..."
         lines.append("| %s | %s | %.1f | %.1f | %.1f | %.2f |" % (
             name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
             float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    if fetch_dir == "-":
+        return "\n".join(lines) + "\n"
     per = {}
     for d, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
         groups = {}
@@ -363,8 +374,8 @@ def rocprof_summary(stats_dir, fetch_dir, write_dir, n, command):
     fetch_groups = per["FETCH_SIZE"][3]
     write_groups = per["WRITE_SIZE"][3]
     machine = []
-    for kind, sym in KIND_SYMBOL.items():
-        sym = sym.format(n=n)
+    for kind in KIND_SYMBOL:
+        sym = kind_symbol(kind, n)
         fk = [k for k in fetch_groups if sym in k]
         wk = [k for k in write_groups if sym in k]
         if not fk or not wk:
@@ -429,10 +440,12 @@ def main():
                     help="print a text summary of rocprofv3 output and exit (no GPU)")
     ap.add_argument("--command", action="append", default=[],
                     help="command line recorded in the --rocprof-summary text")
+    ap.add_argument("--summary-title", default="ITA passes",
+                    help="title of the --rocprof-summary text")
     args = ap.parse_args()
 
     if args.rocprof_summary:
-        print(rocprof_summary(*args.rocprof_summary, args.size, args.command))
+        print(rocprof_summary(*args.rocprof_summary, args.size, args.command, args.summary_title))
         return
 
     if args.gpus != 1:
@@ -494,7 +507,7 @@ def main():
         # passes of M and G are one kernel and are counted together.
         by_sym = {}
         for kind, kd in kernels.items():
-            sym = KIND_SYMBOL[kind].format(n=shape[1] if kind.startswith("row") else shape[0])
+            sym = kind_symbol(kind, shape[1] if kind.startswith("row") else shape[0])
             agg = by_sym.setdefault(sym, {"kinds": [], "ms": 0.0, "cnt": 0, "algo_GB": kd["algo_GB"]})
             agg["kinds"].append(kind)
             agg["ms"] += kd["total_ms"]

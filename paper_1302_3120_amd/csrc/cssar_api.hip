@@ -123,16 +123,17 @@ int occupancy(const void* fn, int block) {
   return n;
 }
 
-// Plan variant of the single-array column pass of each kind.  With
-// CSSAR_COL_V4096 = 1 the forward column passes at 4096 use the
-// split-exchange plan (two workgroups per CU); measured slower on MI355X
-// (update 103 vs 94 us, residual 112 vs 106 us), so variant 0 is the
-// default; the adjoint passes always keep variant 0.
+// Plan variant of the single-array column pass of each kind.  At 4096 the
+// residual pass runs variant 1 (32 elements per thread, 512 threads, the
+// next tile's input loaded during the transforms): 100 us against 107 with
+// variant 0 on MI355X, where variant 1 is slower for the update pass (102
+// against 95: its hoisted twiddles need 16 elements per thread) and the
+// first forward pass.  CSSAR_COL_V4096 = 0 keeps variant 0 for every pass.
 #ifndef CSSAR_COL_V4096
-#define CSSAR_COL_V4096 0
+#define CSSAR_COL_V4096 1
 #endif
 int column_variant(int n, int which) {
-  if (n == 4096 && which <= CK_R) return CSSAR_COL_V4096;
+  if (n == 4096 && which == CK_R) return CSSAR_COL_V4096;
   return 0;
 }
 

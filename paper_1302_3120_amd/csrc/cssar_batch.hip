@@ -379,6 +379,15 @@ int cssar_make_batch(cssar_op* const* ops, int count, cssar_batch** out) {
       b->groups[it->second].scenes.push_back(s);
     }
   }
+  // default plans: those of the single-array solver (same per-line arithmetic)
+  for (auto& g : b->groups) {
+    if (g.row) continue;
+    for (int tk : {(int)TK_R, (int)TK_A}) {
+      const int v = column_variant(g.n, tk == TK_R ? CK_R : CK_A);
+      const KernelTable* kt = table_for(g.n, v);
+      if (kt && variant_fits(b, g, kt)) g.ch[tk].variant = v;
+    }
+  }
   // table block layout: per used slot, the argument array and the prefix sums
   size_t tb = 0;
   for (auto& g : b->groups) {

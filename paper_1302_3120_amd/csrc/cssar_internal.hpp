@@ -32,6 +32,8 @@ const KernelTable* table_for(int n, int v = 0);
 size_t align256(size_t n);
 int occupancy(const void* fn, int block);
 int grid_for(int work, int cus, int per_cu);
+// Plan variant the single-array column pass of kind which uses at length n.
+int column_variant(int n, int which);
 
 }  // namespace detail
 }  // namespace cssar

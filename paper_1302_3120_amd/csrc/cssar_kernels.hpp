@@ -724,13 +724,23 @@ __global__ __launch_bounds__(P::RT) void row_adj_kernel(RowArgs a) {
 // ---------------------------------------------------------- column pass --
 // One tile (C adjacent columns) of a column pass of array a.  Returns the
 // thread's share of the tile's squared norm (FWD with the mask, R).
-// Software pipelining of the update pass: Xt of the next tile is loaded
-// while this tile is transformed, into registers that are free at that
-// point, so one workgroup per compute unit keeps HBM busy during its FFTs.
-// (The residual pass has no free registers for it; split plans get the
-// overlap from a second workgroup instead.)
+// Software pipelining: the next tile's first input (Xt for the update pass,
+// W for the residual pass) is loaded while this tile is transformed, into
+// registers that are free at that point, so one workgroup per compute unit
+// keeps HBM busy during its FFTs.  The residual pass has room for it only
+// with 32 elements per thread and at least 4 columns per tile (256 VGPRs
+// per lane at two waves per SIMD); split plans get the overlap from a second
+// workgroup instead.
+#ifndef CSSAR_PIPE_R
+#define CSSAR_PIPE_R 1
+#endif
+#ifndef CSSAR_PIPE_R_LATEY
+#define CSSAR_PIPE_R_LATEY 0
+#endif
 template <class P, int MODE>
-constexpr bool col_pipelined() { return MODE == COL_A && !P::SPLIT; }
+constexpr bool col_pipelined() {
+  return (MODE == COL_A || (CSSAR_PIPE_R && MODE == COL_R && P::E >= 32 && P::C >= 4)) && !P::SPLIT;
+}
 
 template <class P, int MODE>
 __device__ __forceinline__ void col_preload(const ColArgs& a, int tile, int b, int c, float2 (&pre)[P::E]) {
@@ -836,7 +846,7 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
     for (int k = 0; k < E; ++k) v[k] = cscale(PIPE ? pre[k] : in0.f2(ai.voff, k * ai.kstep), a.scale);
     // (split plans and screened passes load m o y after the inverse
     // transform: registers)
-    if constexpr ((MODE == COL_R && !P::SPLIT && !SCR && !HT) || MODE == COL_U) {
+    if constexpr ((MODE == COL_R && !P::SPLIT && !SCR && !HT && !(PIPE && CSSAR_PIPE_R_LATEY)) || MODE == COL_U) {
 #pragma unroll
       for (int k = 0; k < E; ++k) y2[k] = yb.f2(ab.voff, k * ab.kstep);
     }
@@ -966,7 +976,7 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
   } else {  // COL_R: GX = F^-1[W] / N_a; R = m o y - m o GX; out = F R
     fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
     // split plans, screened passes: m o y in chunks of 8 after the transform
-    constexpr bool late = P::SPLIT || SCR || HT;
+    constexpr bool late = P::SPLIT || SCR || HT || (PIPE && CSSAR_PIPE_R_LATEY);
     constexpr int YC = late ? 8 : E;
 #pragma unroll
     for (int k0 = 0; k0 < E; k0 += YC) {
