@@ -123,17 +123,25 @@ int occupancy(const void* fn, int block) {
   return n;
 }
 
-// Plan variant of the single-array column pass of each kind.  At 4096 the
-// residual pass runs variant 1 (32 elements per thread, 512 threads, the
-// next tile's input loaded during the transforms): 100 us against 107 with
-// variant 0 on MI355X, where variant 1 is slower for the update pass (102
-// against 95: its hoisted twiddles need 16 elements per thread) and the
-// first forward pass.  CSSAR_COL_V4096 = 0 keeps variant 0 for every pass.
+// Plan variant of the single-array column pass of each kind (also the
+// batched solver's default).  At 4096 the residual pass runs variant 1 (32
+// elements per thread, 512 threads, the next tile's input loaded during the
+// transforms): 100 us against 107 with variant 0 on MI355X, where variant 1
+// is slower for the update pass (102 against 95: its hoisted twiddles need
+// 16 elements per thread) and the first forward pass.  At 2048 the update
+// pass runs variant 1 (4-column tiles, two workgroups per compute unit):
+// 23.8 against 26.9 us at 2048 x 2048, the residual pass 38.4 against 37.2.
+// CSSAR_COL_V4096 / CSSAR_COL_V2048 = 0 keep variant 0 for every pass.
 #ifndef CSSAR_COL_V4096
 #define CSSAR_COL_V4096 1
 #endif
+#ifndef CSSAR_COL_V2048
+#define CSSAR_COL_V2048 1
+#endif
 int column_variant(int n, int which) {
   if (n == 4096 && which == CK_R) return CSSAR_COL_V4096;
+  // (the threshold adjoint recomputes the update pass's V: same plan, same support)
+  if (n == 2048 && (which == CK_A || which == CK_VB)) return CSSAR_COL_V2048;
   return 0;
 }
 

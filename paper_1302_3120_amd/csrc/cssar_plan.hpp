@@ -60,7 +60,7 @@ CSSAR_PLAN(1024, 1, 32, 16, 256, 16, 16, 4)
 CSSAR_PLAN(1536, 0, 24, 4, 128, 3, 8, 8, 8)
 CSSAR_PLAN(1536, 1, 24, 8, 256, 3, 8, 8, 8)
 CSSAR_PLAN(2048, 0, 16, 8, 256, 16, 16, 8)
-CSSAR_PLAN(2048, 1, 32, 8, 256, 16, 16, 8)
+CSSAR_PLAN(2048, 1, 16, 4, 256, 16, 16, 8)
 CSSAR_PLAN(3072, 0, 24, 4, 512, 3, 8, 8, 8, 2)
 CSSAR_PLAN(4096, 0, CSSAR_E4096, CSSAR_C4096, CSSAR_RT4096, 16, 16, 16)
 #ifndef CSSAR_SPLIT4096V1
