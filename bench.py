@@ -543,7 +543,7 @@ def main():
         rec["differentiated"] = bench_grad(5, dev)
 
     if not args.no_cpu_baseline:
-        log("bench: timing the FP64 oracle on the host (one iteration)")
+        log("bench: timing the FP64 oracle on the host (three iterations)")
         rec["cpu_baseline"] = cpu_baseline(shape, 1234)
 
     print(json.dumps(rec), flush=True)
