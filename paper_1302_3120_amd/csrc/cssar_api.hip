@@ -138,7 +138,20 @@ int occupancy(const void* fn, int block) {
 #ifndef CSSAR_COL_V2048
 #define CSSAR_COL_V2048 1
 #endif
+// 8192: four-line units through half the LDS (variant 1) for the row passes
+// of the chirp-scaling chain (387 against 527-576 us at 8192 x 8192) and the
+// forward and residual column passes (736 against 949, 498 against 514 us);
+// the update pass keeps the two-column plan (529 against 577 us); 0 keeps
+// variant 0 everywhere.
+#ifndef CSSAR_V8192
+#define CSSAR_V8192 1
+#endif
+int row_variant(int n) { return n == 8192 ? CSSAR_V8192 : 0; }
 int column_variant(int n, int which) {
+  // 8192: the forward, inverse and residual passes on four-column tiles (the
+  // update pass and the passes sharing its support decisions or layout keep
+  // variant 0, which measured faster for them)
+  if (n == 8192) return (which == CK_FWD || which == CK_INV || which == CK_R) ? CSSAR_V8192 : 0;
   if (n == 4096 && which == CK_R) return CSSAR_COL_V4096;
   // (the threshold adjoint recomputes the update pass's V: same plan, same support)
   if (n == 2048 && (which == CK_A || which == CK_VB)) return CSSAR_COL_V2048;
@@ -202,8 +215,8 @@ hipEvent_t take_event(cssar_op* op) {
 
 int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s) {
   if (op->chain == CSSAR_CHAIN_RDA)
-    return timed(op, a.conj ? 1 : 0, s, [&] { return op->kr->row_rda[a.conj ? 1 : 0](a, op->grid_row, s); });
-  return timed(op, a.conj ? 1 : 0, s, [&] { return op->kr->row(a, op->grid_row, s); });
+    return timed(op, a.conj ? 1 : 0, s, [&] { return op->kr->row_rda[a.conj ? 1 : 0](a, op->grid_rda, s); });
+  return timed(op, a.conj ? 1 : 0, s, [&] { return op->krow->row(a, op->grid_row, s); });
 }
 
 int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
@@ -211,7 +224,7 @@ int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
 }
 
 int launch_row_mid(cssar_op* op, const RowArgs& a, hipStream_t s) {
-  return timed(op, a.conj ? 1 : 0, s, [&] { return op->kr->row_mid(a, op->grid_row, s); });
+  return timed(op, a.conj ? 1 : 0, s, [&] { return op->krow->row_mid(a, op->grid_row, s); });
 }
 
 int launch_col_scr(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
@@ -322,9 +335,14 @@ int make_operator_impl(const cssar_params* p, int n_az, int n_rg, int chain, int
   if (e == hipSuccess) e = hipMemset(op->counter, 0, 4 * sizeof(unsigned));
   if (e != hipSuccess) return cleanup(fail(CSSAR_EHIP, "uploading operator tables: %s", hipGetErrorString(e)));
 
+  // the chirp-scaling row passes may run another plan variant; the
+  // range-Doppler and adjoint row passes keep variant 0
+  op->krow = table_for(n_rg, row_variant(n_rg));
+  if (!op->krow || n_az % op->krow->LR != 0) op->krow = kr;
   const int row_work = (n_az + kr->LR - 1) / kr->LR;
-  op->grid_row = grid_for(row_work, op->cus,
-                          occupancy(chain == CSSAR_CHAIN_RDA ? kr->row_rda_fn[0] : kr->row_fn, kr->RT));
+  op->grid_row = grid_for((n_az + op->krow->LR - 1) / op->krow->LR, op->cus,
+                          occupancy(op->krow->row_fn, op->krow->RT));
+  op->grid_rda = grid_for(row_work, op->cus, occupancy(kr->row_rda_fn[0], kr->RT));
   for (int c = 0; c < 2; ++c)
     op->grid_adj[c] = std::min(grid_for(row_work, op->cus, occupancy(kr->row_adj_fn[c], kr->RT)), kMaxPartials / 2);
   for (int w = 0; w < CK_COUNT; ++w) {

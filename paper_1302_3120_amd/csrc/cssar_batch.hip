@@ -381,7 +381,11 @@ int cssar_make_batch(cssar_op* const* ops, int count, cssar_batch** out) {
   }
   // default plans: those of the single-array solver (same per-line arithmetic)
   for (auto& g : b->groups) {
-    if (g.row) continue;
+    if (g.row) {
+      const KernelTable* kt = table_for(g.n, row_variant(g.n));
+      if (kt && variant_fits(b, g, kt)) g.ch[TK_ROW].variant = row_variant(g.n);
+      continue;
+    }
     for (int tk : {(int)TK_R, (int)TK_A}) {
       const int v = column_variant(g.n, tk == TK_R ? CK_R : CK_A);
       const KernelTable* kt = table_for(g.n, v);

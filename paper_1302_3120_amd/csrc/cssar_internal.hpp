@@ -32,8 +32,10 @@ const KernelTable* table_for(int n, int v = 0);
 size_t align256(size_t n);
 int occupancy(const void* fn, int block);
 int grid_for(int work, int cus, int per_cu);
-// Plan variant the single-array column pass of kind which uses at length n.
+// Plan variant the single-array column pass of kind which uses at length n,
+// and the one of the chirp-scaling row passes.
 int column_variant(int n, int which);
+int row_variant(int n);
 
 }  // namespace detail
 }  // namespace cssar
@@ -47,7 +49,8 @@ struct cssar_op {
   int device = 0;
   int cus = 0;
   const cssar::KernelTable* ka = nullptr;  // azimuth length N_a (column passes)
-  const cssar::KernelTable* kr = nullptr;  // range length N_r (row passes)
+  const cssar::KernelTable* kr = nullptr;  // range length N_r, variant 0 (adjoint, range-Doppler rows)
+  const cssar::KernelTable* krow = nullptr;  // range length N_r (chirp-scaling row passes)
   const cssar::KernelTable* kcol[cssar::CK_COUNT] = {};  // per column-pass kind (N_a)
   double2* rowc1 = nullptr;         // per Doppler bin: Phi1 (a1, d1); range-Doppler: migration (a, b)
   double2* rowc2 = nullptr;         //                  Phi2 (a2, b2)
@@ -58,6 +61,7 @@ struct cssar_op {
   unsigned* counter = nullptr;      // [0] last-block counter, [1] status bits
   float* rowd = nullptr;            // per Doppler bin: 18 screen-derivative coefficients
   int grid_row = 0;
+  int grid_rda = 0;
   int grid_col[cssar::CK_COUNT] = {};
   int grid_adj[2] = {};
   // optional per-launch HIP event timing (cssar_profile_enable)

@@ -281,7 +281,7 @@ struct RowLane {
 template <class P>
 struct RowLds {
   static constexpr int LI = P::LR >= 4 ? 4 : P::LR;
-  static constexpr int LS = LdsSize<LI, P::N>::value;
+  static constexpr int LS = LdsSize<LI, P::SPLIT ? P::N / 2 : P::N>::value;  // split: half lines
   static constexpr int size = (P::LR / LI) * LS;
 };
 
@@ -355,10 +355,10 @@ __device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane
     if (conj) screen(tau_t{}, phi3_quad(c3, a, b, T), 2, 1.0f);
     else screen(tau_t{}, phi1_quad(c1, a, b, T), 0, 1.0f);
   }
-  fft_line<P, false, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
+  fft_line<P, false, LI, TwLds, 0, HS, P::SPLIT>(v, lb, lc, lds + loff, tws, hp);
   screen(freq_t{}, phi2_quad(c2, b, T), 1, a.scale);
   asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
-  fft_line<P, true, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
+  fft_line<P, true, LI, TwLds, 0, HS, P::SPLIT>(v, lb, lc, lds + loff, tws, hp);
   // second range-Doppler screen: Phi3 (M) or Phi1* (G)
   if constexpr (!MID) {
     if (conj) screen(tau_t{}, phi1_quad(c1, a, b, T), 0, 1.0f);
@@ -608,8 +608,11 @@ __global__ __launch_bounds__(P::RT) void row_rda_kernel(RowArgs a) {
   if constexpr (hoisted_pass<P>() >= 0)
     hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(ln.b, TwLds{twl, twl + 64});
   const int units = a.na / P::LR;
-  for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x)
-    row_rda_unit<P, CONJ, KT>(a, gi, ln, lds, twl, hp);
+  // (it stages whole lines in LDS: the host uses it with unsplit plans only)
+  if constexpr (!P::SPLIT) {
+    for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x)
+      row_rda_unit<P, CONJ, KT>(a, gi, ln, lds, twl, hp);
+  }
 }
 
 // ------------------------------------------------------ adjoint row pass --
@@ -680,23 +683,23 @@ __device__ __forceinline__ void row_adj_unit(const RowArgs& a, int gi, const Row
 #pragma unroll
   for (int k = 0; k < E; ++k) f[k] = x0[k];
   apply_quad<E, false>(f, cj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), cj, 1.0f);
-  fft_line<P, false, LI>(f, lb, lc, lds + loff, tws);
+  fft_line<P, false, LI, TwLds, P::SPLIT>(f, lb, lc, lds + loff, tws);
   apply_quad<E, true>(f, phi2_quad(c2, b, T), cj, a.scale);
 #pragma unroll
   for (int k = 0; k < E; ++k) fm[k] = f[k];
   asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
-  fft_line<P, true, LI>(f, lb, lc, lds + loff, tws);
+  fft_line<P, true, LI, TwLds, P::SPLIT>(f, lb, lc, lds + loff, tws);
   // adjoint chain: its first screen is the conjugate of the forward's last
 #pragma unroll
   for (int k = 0; k < E; ++k) w[k] = in2.f2(vo, T * k * 32);
   apply_quad<E, false>(w, cj ? phi1_quad(c1, a, b, T) : phi3_quad(c3, a, b, T), !cj, 1.0f);
   pair_stage<E, T, false>(f, w, d + s_last * 3, d + 9 + s_last * 3, b, sgn, acc_ka, acc_kr);
   asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
-  fft_line<P, false, LI>(w, lb, lc, lds + loff, tws);
+  fft_line<P, false, LI, TwLds, P::SPLIT>(w, lb, lc, lds + loff, tws);
   pair_stage<E, T, true>(fm, w, d + 3, d + 12, b, sgn, acc_ka, acc_kr);
   apply_quad<E, true>(w, phi2_quad(c2, b, T), !cj, a.scale);
   asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
-  fft_line<P, true, LI>(w, lb, lc, lds + loff, tws);
+  fft_line<P, true, LI, TwLds, P::SPLIT>(w, lb, lc, lds + loff, tws);
   apply_quad<E, false>(w, cj ? phi3_quad(c3, a, b, T) : phi1_quad(c1, a, b, T), !cj, 1.0f);
   pair_stage<E, T, false>(x0, w, d + s_first * 3, d + 9 + s_first * 3, b, sgn, acc_ka, acc_kr);
 #pragma unroll
@@ -1017,7 +1020,9 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
 template <class P>
 struct ColLds {
   static constexpr int size = LdsSize<P::C, P::SPLIT ? P::N / 2 : P::N>::value;
-  static constexpr int waves_per_eu = P::SPLIT ? 2 * P::CT / 256 : 1;
+  // workgroups per CU the LDS allows (160 KB, some for twiddles and sums)
+  static constexpr int wgs = size * 8 <= 78 * 1024 ? 2 : 1;
+  static constexpr int waves_per_eu = P::SPLIT ? wgs * P::CT / 256 : 1;
 };
 
 template <class P, int MODE, bool SCR>

@@ -5,7 +5,9 @@
 // in LDS); row passes process LR rows per workgroup.  Variant 0 is the
 // default of every length; variant 1, where it exists, is an alternative
 // schedule (other E, radices, tile width or rows per workgroup) that the
-// batched solver's autotuner may pick after measuring both.
+// batched solver's autotuner may pick after measuring both, and that the
+// single-array passes use where it measured faster.  A split plan (SPLIT)
+// exchanges through half the LDS, in two rounds, for rows and columns.
 #pragma once
 
 namespace cssar {
@@ -68,6 +70,8 @@ CSSAR_PLAN(4096, 0, CSSAR_E4096, CSSAR_C4096, CSSAR_RT4096, 16, 16, 16)
 #endif
 CSSAR_PLAN_S(4096, 1, 32, 4, 256, CSSAR_SPLIT4096V1, 16, 16, 16)
 CSSAR_PLAN(8192, 0, 32, 2, 256, 16, 16, 16, 2)
+// four-line units of 8192 points through half the LDS (rows and columns)
+CSSAR_PLAN_S(8192, 1, 32, 4, 1024, true, 16, 16, 16, 2)
 
 #undef CSSAR_PLAN
 #undef CSSAR_PLAN_S
@@ -87,7 +91,8 @@ constexpr bool plan_ok() {
 // Every (length, variant) pair that is compiled.
 #define CSSAR_FOR_EACH_PLAN(X)                                                    \
   X(64, 0) X(128, 0) X(256, 0) X(512, 0) X(512, 1) X(768, 0) X(1024, 0) X(1024, 1) \
-  X(1536, 0) X(1536, 1) X(2048, 0) X(2048, 1) X(3072, 0) X(4096, 0) X(4096, 1) X(8192, 0)
+  X(1536, 0) X(1536, 1) X(2048, 0) X(2048, 1) X(3072, 0) X(4096, 0) X(4096, 1) X(8192, 0) \
+  X(8192, 1)
 
 #define CSSAR_CHECK_PLAN(NN, VV) static_assert(plan_ok<Plan<NN, VV>>(), "plan");
 CSSAR_FOR_EACH_PLAN(CSSAR_CHECK_PLAN)
