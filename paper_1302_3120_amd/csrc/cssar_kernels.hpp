@@ -737,9 +737,6 @@ __global__ __launch_bounds__(P::RT) void row_adj_kernel(RowArgs a) {
 #ifndef CSSAR_PIPE_R
 #define CSSAR_PIPE_R 1
 #endif
-#ifndef CSSAR_PIPE_R_LATEY
-#define CSSAR_PIPE_R_LATEY 0
-#endif
 template <class P, int MODE>
 constexpr bool col_pipelined() {
   return (MODE == COL_A || (CSSAR_PIPE_R && MODE == COL_R && P::E >= 32 && P::C >= 4)) && !P::SPLIT;
@@ -849,7 +846,7 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
     for (int k = 0; k < E; ++k) v[k] = cscale(PIPE ? pre[k] : in0.f2(ai.voff, k * ai.kstep), a.scale);
     // (split plans and screened passes load m o y after the inverse
     // transform: registers)
-    if constexpr ((MODE == COL_R && !P::SPLIT && !SCR && !HT && !(PIPE && CSSAR_PIPE_R_LATEY)) || MODE == COL_U) {
+    if constexpr ((MODE == COL_R && !P::SPLIT && !SCR && !HT) || MODE == COL_U) {
 #pragma unroll
       for (int k = 0; k < E; ++k) y2[k] = yb.f2(ab.voff, k * ab.kstep);
     }
@@ -979,7 +976,7 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
   } else {  // COL_R: GX = F^-1[W] / N_a; R = m o y - m o GX; out = F R
     fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
     // split plans, screened passes: m o y in chunks of 8 after the transform
-    constexpr bool late = P::SPLIT || SCR || HT || (PIPE && CSSAR_PIPE_R_LATEY);
+    constexpr bool late = P::SPLIT || SCR || HT;
     constexpr int YC = late ? 8 : E;
 #pragma unroll
     for (int k0 = 0; k0 < E; k0 += YC) {
