@@ -63,6 +63,7 @@ def _run(op, y, mask, k, iters, dev):
     (STRESS, (128, 512), 40, 6),
     (P, (512, 256), 60, 6),
     (P, (768, 1536), 80, 4),
+    (P, (8192, 64), 40, 4),  # 8192-point columns: the four-column split plan for F and R
 ])
 def test_adaptive_matches_oracle(dev, params, shape, k, iters):
     import paper_1302_3120_amd as pk

@@ -56,7 +56,9 @@ def _random_batch(shapes, seed, dev):
     return ops, ys, masks, bits, lams
 
 
-SMALL = [(256, 512), (512, 256), (768, 1024), (1024, 768), (512, 512), (256, 256), (1536, 512)]
+# (2048 and 4096 columns run plan variant 1 for the update / residual pass by default)
+SMALL = [(256, 512), (512, 256), (768, 1024), (1024, 768), (512, 512), (256, 256), (1536, 512),
+         (2048, 256), (4096, 64)]
 
 
 def test_batched_equals_per_scene_bitwise(dev):

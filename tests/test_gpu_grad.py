@@ -87,6 +87,7 @@ def test_checkpointed_forward_equals_solve(dev):
 @pytest.mark.parametrize("params,shape,K,every", [
     (P, (128, 256), 6, 2),
     (inputs.RADAR_LBAND_STRESS, (256, 128), 5, 5),
+    (P, (2048, 128), 3, 2),  # 2048-point columns: the update pass and its adjoint on variant 1
 ])
 def test_gradient_matches_oracle(dev, params, shape, K, every):
     say(f"[gpu] gradient vs oracle {shape} K={K} every={every} fc={params['fc']:.3g}")
