@@ -14,10 +14,11 @@
 //   D: dX on the support -> ||dX_G||^2 and F dX_G;  row pass of G on it;
 //   N: ||m o G dX_G||^2 -> mu_i (device memory);
 //   V: V = X + mu_i dX (spatial);
-//   the selection of the (k+1)-th largest |V|^2: three histogram passes over
+//   the selection of the (k+1)-th largest |V|^2: three histogram levels over
 //   V (11, 11 and 10 bits of the FP32 bit pattern, which orders non-negative
-//   floats as their values), each followed by a one-workgroup pass that finds
-//   the bucket holding the rank;
+//   floats as their values; the first counted by the V pass itself, the
+//   others by passes over V), each followed by a one-workgroup pass that
+//   finds the bucket holding the rank;
 //   T: X+ = S_sigma(V), the support bits of X+, F X+.
 // Nothing returns to the host between iterations.
 #include <algorithm>
@@ -158,8 +159,10 @@ int select_threshold(cssar_op* op, const float2* V, AdaptState* st, float* lambd
   const int grid = std::max(1, std::min(op->cus * 4, (op->na / 4) * op->nr / 2 / kSelectThreads + 1));
   return timed(op, 15, s, [&] {
     for (int level = 0; level < 3; ++level) {
-      hipLaunchKernelGGL(select_hist_kernel, dim3(grid), dim3(kSelectThreads), 0, s, (const float4*)V, op->na,
-                         op->nr, st, level);
+      // (the value pass that wrote V has counted level 0)
+      if (level > 0)
+        hipLaunchKernelGGL(select_hist_kernel, dim3(grid), dim3(kSelectThreads), 0, s, (const float4*)V,
+                           op->na, op->nr, st, level);
       hipLaunchKernelGGL(select_find_kernel, dim3(1), dim3(kFindThreads), 0, s, st, level,
                          level == 2 ? lambda_out : nullptr);
     }

@@ -803,7 +803,7 @@ __device__ __forceinline__ MaskAddr mask_addr(int b, int j, int T, int nr) {
 template <class P, int MODE, bool PIPE = false, bool SCR = false, bool HT = false>
 __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int c, float2* lds,
                                           const float2* twl, float2 (&pre)[P::E], int next,
-                                          const TwPowers& hp) {
+                                          const TwPowers& hp, unsigned* hist0 = nullptr) {
   constexpr int HSC = HT ? hoisted_pass<P>() : -1;
   constexpr int N = P::N, E = P::E, T = P::T, C = P::C;
   const uint32_t rmb = clamp_bytes((size_t)N * a.nr * 8), b4b = clamp_bytes(b4_bytes(N, a.nr));
@@ -958,6 +958,11 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
     }
   } else if constexpr (MODE == COL_V) {
     fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);  // V (spatial)
+    // first level of the selection of the threshold: histogram of the top
+    // 11 bits of |V|^2 (computed as the selection and threshold passes do)
+#pragma unroll
+    for (int k = 0; k < E; ++k)
+      atomicAdd(&hist0[__float_as_uint(fmaf(v[k].x, v[k].x, v[k].y * v[k].y)) >> 21], 1u);
   } else if constexpr (MODE == COL_T) {
     // X+ = S_sigma(V): kept where |V|^2 > sigma^2 (sigma^2 the selected
     // (k+1)-th largest |V|^2, computed the same way); support bit = X+ != 0
@@ -1041,13 +1046,24 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   if constexpr (HT) hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(b, TwLds{twl, twl + 64});
   float acc = 0.f;
   float2 pre[P::E];
+  // the value pass (adaptive threshold) also counts the first selection level
+  __shared__ unsigned hist0[MODE == COL_V ? 2048 : 1];
+  if constexpr (MODE == COL_V) {
+    for (int i = threadIdx.x; i < 2048; i += CT) hist0[i] = 0u;
+    __syncthreads();
+  }
   int tile = xcd_logical_block();
   if constexpr (PIPE) {
     if (tile < ntiles) col_preload<P, MODE>(a, tile, b, c, pre);
   }
   for (; tile < ntiles; tile += gridDim.x) {
     const int next = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : -1;
-    acc += col_unit<P, MODE, PIPE, SCR, HT>(a, tile, b, c, lds, twl, pre, next, hp);
+    acc += col_unit<P, MODE, PIPE, SCR, HT>(a, tile, b, c, lds, twl, pre, next, hp, hist0);
+  }
+  if constexpr (MODE == COL_V) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2048; i += CT)
+      if (hist0[i]) atomicAdd(&a.ad->hist[i], hist0[i]);
   }
   const bool want_norm = (MODE == COL_R) || (MODE == COL_FWD && (a.flags & 1));
   if (want_norm) {
