@@ -139,3 +139,66 @@ def ita_adaptive(y, mask, k, iters, geom, x0=None):
         mus.append(mu)
         lams.append(sigma / mu)
     return x, resid, mus, lams
+
+
+def safeguard_bound(x_new, x, mask, geom, c):
+    """The step bound of the support-change safeguard of the cited normalized
+    iterative hard thresholding (Section IV.B cites it for mu_i):
+
+        omega = (1 - c) ||X+ - X||^2 / ||m o G(X+ - X)||^2,
+
+    +inf when the denominator is 0 (no measured change: no bound)."""
+    d = np.asarray(x_new, dtype=np.complex128) - np.asarray(x, dtype=np.complex128)
+    num = float(np.vdot(d, d).real)
+    gd = np.asarray(mask, dtype=np.float64) * _G(d, geom)
+    den = float(np.vdot(gd, gd).real)
+    return (1.0 - c) * num / den if den > 0.0 else np.inf
+
+
+def ita_adaptive_safeguarded(y, mask, k, iters, geom, c=0.01, kappa=2.0, max_shrinks=2, x0=None):
+    """ita_adaptive with the support-change safeguard of the cited normalized
+    iterative hard thresholding, applied to the paper's soft-threshold step
+    (whose support is the k largest |V|, as the hard threshold's):
+
+        V = X + mu dX,  X+ = E_{1, |V|_{k+1}}(V)
+        while supp X+ != supp X and fewer than max_shrinks shrinks so far:
+            if mu <= safeguard_bound(X+, X): stop
+            mu <- mu / (kappa (1 - c));  V, X+ again with the new mu
+
+    kappa (1 - c) > 1.  With mu <= omega the step satisfies the descent
+    condition of that method; max_shrinks bounds the loop (the cited method
+    has no bound).  Returns (X^(iters), [||R^(i)||^2], [mu_i], [lambda_i],
+    [shrinks_i], [mu / omega at each bound test])."""
+    if not (0.0 < c < 1.0) or not (kappa * (1.0 - c) > 1.0):
+        raise ValueError("need 0 < c < 1 and kappa (1 - c) > 1")
+    y = np.asarray(y, dtype=np.complex128)
+    m = np.asarray(mask, dtype=np.float64)
+    x = np.zeros_like(y) if x0 is None else np.array(x0, dtype=np.complex128)
+    resid, mus, lams, shrinks, ratios = [], [], [], [], []
+    for _ in range(int(iters)):
+        r = m * (y - _G(x, geom)) if np.any(x) else m * y
+        resid.append(float(np.vdot(r, r).real))
+        dx = _M(r, geom)
+        mu = normalized_step(dx, x != 0, mask, geom)
+        support = x != 0
+
+        def step(mu):
+            v = x + mu * dx
+            sigma = kth_largest_magnitude(v, int(k) + 1)
+            return soft_threshold(v, sigma), sigma
+
+        x_new, sigma = step(mu)
+        s = 0
+        while s < max_shrinks and np.any((x_new != 0) != support):
+            omega = safeguard_bound(x_new, x, mask, geom, c)
+            ratios.append(mu / omega)
+            if mu <= omega:
+                break
+            mu = mu / (kappa * (1.0 - c))
+            s += 1
+            x_new, sigma = step(mu)
+        x = x_new
+        mus.append(mu)
+        lams.append(sigma / mu)
+        shrinks.append(s)
+    return x, resid, mus, lams, shrinks, ratios
