@@ -117,6 +117,8 @@ int cssar_destroy_operator(cssar_op* op);
  *   mode 2: cssar_ita_solve_adaptive         (four arrays in the blocked layout, the
  *           support bits (4 N_a N_r / E bytes, E the column plan's elements per
  *           thread) and 8.5 KB of selection state)
+ *   mode 3: cssar_ita_solve_safeguarded      (six arrays in the blocked layout, two
+ *           sets of support bits and the selection state)
  * The blocked layout holds 4 x 4 blocks of 128 bytes with a 128-byte pad per
  * block row: (N_a/4) (32 N_r + 128) bytes per array.  Returns 0 for a NULL
  * operator or an unknown mode. */
@@ -164,6 +166,32 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
 int cssar_ita_solve_adaptive(cssar_op* op, const void* y, const void* mask_bits, long k, int iters,
                              void* x_out, float* mu_hist, float* lambda_hist, float* resid_hist,
                              void* ws, void* stream);
+
+/* Largest max_shrinks of cssar_ita_solve_safeguarded. */
+#define CSSAR_MAX_SHRINKS 16
+
+/* cssar_ita_solve_adaptive with the support-change safeguard of the
+ * normalized iterative hard thresholding that Section IV.B cites for its
+ * step (the paper states no safeguard; the bound is that method's): after
+ * the step X+ = S_{lambda_t mu_t}(X + mu_t dX), if the support of X+ differs
+ * from that of X,
+ *   omega = (1 - c) ||X+ - X||^2 / ||m o G(X+ - X)||^2   (no bound if the
+ *           denominator is 0),
+ * and while mu_t > omega, mu_t <- mu_t / (kappa (1 - c)) and the step
+ * (V, lambda_t, X+) is taken again, at most max_shrinks times per
+ * iteration.  An accepted step lowers 1/2 ||m o (y - G X)||^2 + lambda_t ||X||_1.
+ * The loop runs on the device: each iteration launches the passes of
+ * max_shrinks further rounds, which return at once when the loop has ended
+ * (support unchanged or mu_t <= omega).  c in (0, 1), kappa (1 - c) > 1
+ * (the Python binding defaults to c = 0.01, kappa = 2, max_shrinks = 2),
+ * 0 <= max_shrinks <= CSSAR_MAX_SHRINKS; CSSAR_EINVAL otherwise.  mu_hist, lambda_hist receive
+ * the accepted step and threshold; shrink_hist: NULL or a device array of
+ * iters ints receiving the shrinks of each iteration.  Other arguments as
+ * cssar_ita_solve_adaptive; ws: cssar_workspace_size(op, 3) bytes. */
+int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bits, long k, int iters,
+                                double c, double kappa, int max_shrinks, void* x_out, float* mu_hist,
+                                float* lambda_hist, float* resid_hist, int* shrink_hist, void* ws,
+                                void* stream);
 
 /* ---------------------------------------------------------------- batch --
  * Many independent scenes (any supported shapes) solved together.  The

@@ -46,7 +46,9 @@ __device__ __forceinline__ unsigned level_prefix(unsigned key, int level) {
 // Histogram of the keys |V|^2 (FP32 bits; V in the blocked layout, pads
 // skipped) at one level, over the keys that match the prefix found so far.
 __global__ __launch_bounds__(kSelectThreads) void select_hist_kernel(const float4* __restrict__ v, int na,
-                                                                     int nr, AdaptState* st, int level) {
+                                                                     int nr, AdaptState* st, int level,
+                                                                     const unsigned* gate) {
+  if (gate && *gate == 0u) return;  // (uniform over the grid)
   __shared__ unsigned h[2048];
   for (int i = threadIdx.x; i < 2048; i += kSelectThreads) h[i] = 0u;
   __syncthreads();
@@ -74,7 +76,8 @@ __global__ __launch_bounds__(kSelectThreads) void select_hist_kernel(const float
 // sigma^2; sigma, lambda = sigma / mu (into lambda_out if not NULL) and the
 // selection state for the next iteration follow.
 __global__ __launch_bounds__(kFindThreads) void select_find_kernel(AdaptState* st, int level,
-                                                                   float* lambda_out) {
+                                                                   float* lambda_out, const unsigned* gate) {
+  if (gate && *gate == 0u) return;
   __shared__ unsigned suf[kFindThreads];
   const int t = threadIdx.x;
   const unsigned h0 = st->hist[2 * t], h1 = st->hist[2 * t + 1];
@@ -132,8 +135,8 @@ __global__ __launch_bounds__(kFindThreads) void select_find_kernel(AdaptState* s
 }
 
 // Selection state at the start of a solve: mu_0 = 1 (the support of X(0) = 0
-// is empty), histogram cleared, rank k + 1.
-__global__ void adapt_init_kernel(AdaptState* st, unsigned k1, float* mu0) {
+// is empty), histogram cleared, rank k + 1; the safeguard's constants.
+__global__ void adapt_init_kernel(AdaptState* st, unsigned k1, float* mu0, double c, double shrink) {
   for (int i = threadIdx.x; i < 2048; i += blockDim.x) st->hist[i] = 0u;
   if (threadIdx.x == 0) {
     st->prefix = 0u;
@@ -144,8 +147,21 @@ __global__ void adapt_init_kernel(AdaptState* st, unsigned k1, float* mu0) {
     st->sigma = 0.0f;
     st->sigma2 = 0.0f;
     st->num = 0.0;
+    st->dnum = 0.0;
+    st->c = c;
+    st->shrink = shrink;
+    st->active = 0u;
+    st->changed = 0u;
+    st->shrinks = 0u;
     if (mu0) mu0[0] = 1.0f;
   }
+}
+
+// Zero n 32-bit words (a kernel rather than a memset node, so the solve can
+// be captured in a graph).
+__global__ void zero_words_kernel(uint32_t* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
 }
 
 // Bytes of the support bits of the adaptive column passes (one word per
@@ -155,16 +171,17 @@ size_t support_bytes(const cssar_op* op) {
   return (size_t)(op->nr / kt->C) * kt->CT * sizeof(uint32_t);
 }
 
-int select_threshold(cssar_op* op, const float2* V, AdaptState* st, float* lambda_out, hipStream_t s) {
+int select_threshold(cssar_op* op, const float2* V, AdaptState* st, float* lambda_out, hipStream_t s,
+                     const unsigned* gate = nullptr) {
   const int grid = std::max(1, std::min(op->cus * 4, (op->na / 4) * op->nr / 2 / kSelectThreads + 1));
   return timed(op, 15, s, [&] {
     for (int level = 0; level < 3; ++level) {
       // (the value pass that wrote V has counted level 0)
       if (level > 0)
         hipLaunchKernelGGL(select_hist_kernel, dim3(grid), dim3(kSelectThreads), 0, s, (const float4*)V,
-                           op->na, op->nr, st, level);
+                           op->na, op->nr, st, level, gate);
       hipLaunchKernelGGL(select_find_kernel, dim3(1), dim3(kFindThreads), 0, s, st, level,
-                         level == 2 ? lambda_out : nullptr);
+                         level == 2 ? lambda_out : nullptr, gate);
     }
     return hipGetLastError();
   });
@@ -195,7 +212,7 @@ int cssar_ita_solve_adaptive(cssar_op* op, const void* y, const void* mask_bits,
   float2* Q = (float2*)(w + 3 * blk); // F_eta dX_G, then F_eta G dX_G
   uint32_t* supp = (uint32_t*)(w + 4 * blk);
   AdaptState* st = (AdaptState*)(w + 4 * blk + align256(support_bytes(op)));
-  hipLaunchKernelGGL(adapt_init_kernel, dim3(1), dim3(256), 0, s, st, k1, mu_hist);
+  hipLaunchKernelGGL(adapt_init_kernel, dim3(1), dim3(256), 0, s, st, k1, mu_hist, 0.0, 1.0);
   HIP_TRY(hipGetLastError());
   ColArgs a = col_args(op);
   a.y = Y;
@@ -246,6 +263,120 @@ int cssar_ita_solve_adaptive(cssar_op* op, const void* y, const void* mask_bits,
     x.flags = last ? 2 : 0;
     x.hist_out = nullptr;
     if ((rc = launch_col(op, CK_T, x, s))) return rc;
+  }
+  return CSSAR_OK;
+}
+
+int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bits, long k, int iters,
+                                double c, double kappa, int max_shrinks, void* x_out, float* mu_hist,
+                                float* lambda_hist, float* resid_hist, int* shrink_hist, void* ws,
+                                void* stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (!y || !mask_bits || !x_out || !ws) return fail(CSSAR_EINVAL, "NULL array");
+  if (iters < 1) return fail(CSSAR_EINVAL, "iters must be >= 1");
+  if (k < 0) return fail(CSSAR_EINVAL, "k must be >= 0");
+  if (!(c > 0.0 && c < 1.0)) return fail(CSSAR_EINVAL, "c must lie in (0, 1)");
+  if (!(kappa * (1.0 - c) > 1.0) || !std::isfinite(kappa))
+    return fail(CSSAR_EINVAL, "kappa (1 - c) must exceed 1");
+  if (max_shrinks < 0 || max_shrinks > CSSAR_MAX_SHRINKS)
+    return fail(CSSAR_EINVAL, "max_shrinks must lie in 0..%d", CSSAR_MAX_SHRINKS);
+  if (x_out == y || x_out == ws || ws == y) return fail(CSSAR_EINVAL, "x_out, y and ws must not alias");
+  const long n = (long)op->na * op->nr;
+  const unsigned k1 = (unsigned)std::min(k, n) + 1u;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t blk = align256(b4_bytes(op->na, op->nr)), sb = align256(support_bytes(op));
+  char* w = (char*)ws;
+  float2* X = (float2*)w;              // F_eta X (blocked layout)
+  float2* P = (float2*)(w + blk);      // pass buffer, then F_eta dX
+  float2* Y = (float2*)(w + 2 * blk);  // m o y (blocked layout, unsampled marked)
+  float2* Q = (float2*)(w + 3 * blk);  // F_eta dX_G, F_eta G dX_G, then V
+  float2* Xn = (float2*)(w + 4 * blk); // F_eta X+
+  float2* Df = (float2*)(w + 5 * blk); // F_eta (X+ - X), then F_eta G(X+ - X)
+  uint32_t* so = (uint32_t*)(w + 6 * blk);       // support bits of X
+  uint32_t* sn = (uint32_t*)(w + 6 * blk + sb);  // support bits of X+
+  AdaptState* st = (AdaptState*)(w + 6 * blk + 2 * sb);
+  const unsigned* active = &st->active;
+  hipLaunchKernelGGL(adapt_init_kernel, dim3(1), dim3(256), 0, s, st, k1, mu_hist, c,
+                     1.0 / (kappa * (1.0 - c)));
+  hipLaunchKernelGGL(zero_words_kernel, dim3(std::max<size_t>(1, std::min<size_t>(1024, sb / 1024))),
+                     dim3(256), 0, s, so, sb / 4);
+  if (shrink_hist)
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(256), 0, s, (uint32_t*)shrink_hist, (size_t)iters);
+  HIP_TRY(hipGetLastError());
+  ColArgs a = col_args(op);
+  a.y = Y;
+  a.mask = (const uint32_t*)mask_bits;
+  a.ad = st;
+  for (int t = 0; t < iters; ++t) {
+    a.hist_out = resid_hist ? resid_hist + t : nullptr;
+    a.supp = so;  // the support of X (read by D)
+    if (t == 0) {
+      ColArgs f = a;  // R(0) = m o y: P = F_eta R, keep m o y
+      f.in0 = (const float2*)y;
+      f.out = P;
+      f.out2 = Y;
+      f.flags = 1 | 4;
+      if ((rc = launch_col(op, CK_FWD, f, s))) return rc;
+    } else {
+      if ((rc = launch_row(op, row_args(op, X, P, 1), s))) return rc;
+      ColArgs r = a;
+      r.in0 = P;
+      r.out = P;
+      if ((rc = launch_col(op, CK_R, r, s))) return rc;
+    }
+    if ((rc = launch_row(op, row_args(op, P, P, 0), s))) return rc;  // P = F_eta dX
+    if (t > 0) {
+      ColArgs d = a;  // Q = F_eta dX_G, ||dX_G||^2
+      d.in0 = P;
+      d.out = Q;
+      d.hist_out = nullptr;
+      if ((rc = launch_col(op, CK_D, d, s))) return rc;
+      if ((rc = launch_row(op, row_args(op, Q, Q, 1), s))) return rc;
+      ColArgs m = a;  // mu = ||dX_G||^2 / ||m o G dX_G||^2; no shrinks yet
+      m.in0 = Q;
+      m.hist_out = mu_hist ? mu_hist + t : nullptr;
+      if ((rc = launch_col(op, CK_N, m, s))) return rc;
+    }
+    // The step, then up to max_shrinks rounds that run only while the
+    // previous round moved the support and its step exceeded the bound.
+    for (int round = 0; round <= max_shrinks; ++round) {
+      const unsigned* gate = round ? active : nullptr;
+      ColArgs v = a;  // V = X + mu dX (spatial, into Q)
+      v.in0 = X;
+      v.in1 = P;
+      v.out = Q;
+      v.flags = t == 0 ? 1 : 0;
+      v.hist_out = nullptr;
+      v.gate = gate;
+      if ((rc = launch_col(op, CK_V, v, s))) return rc;
+      if ((rc = select_threshold(op, Q, st, lambda_hist ? lambda_hist + t : nullptr, s, gate))) return rc;
+      ColArgs x = a;  // X+ = S_sigma(V) -> F_eta X+; support change; F_eta (X+ - X)
+      x.in0 = Q;
+      x.in1 = X;
+      x.out = Xn;
+      x.out2 = Df;
+      x.supp = sn;
+      x.supp_old = so;
+      x.out3 = (float2*)x_out;  // the last iteration's X+ (each round overwrites it)
+      x.flags = 4 | (t == 0 ? 1 : 0) | (t == iters - 1 ? 16 : 0);
+      x.hist_out = nullptr;
+      x.gate = gate;
+      if ((rc = launch_col(op, CK_T, x, s))) return rc;
+      if (round == max_shrinks) break;
+      RowArgs g = row_args(op, Df, Df, 1);  // F_eta G(X+ - X), after a support change
+      g.gate = active;
+      if ((rc = launch_row(op, g, s))) return rc;
+      ColArgs b = a;  // the bound; shrink mu or end the loop
+      b.in0 = Df;
+      b.flags = 8;
+      b.hist_out = mu_hist ? mu_hist + t : nullptr;
+      b.count_out = shrink_hist ? shrink_hist + t : nullptr;
+      b.gate = active;
+      if ((rc = launch_col(op, CK_N, b, s))) return rc;
+    }
+    std::swap(X, Xn);
+    std::swap(so, sn);
   }
   return CSSAR_OK;
 }

@@ -393,6 +393,8 @@ size_t cssar_workspace_size(const cssar_op* op, int mode) {
       return 3 * blk;
     case 2:
       return 4 * blk + align256(support_bytes(op)) + align256(sizeof(AdaptState));
+    case 3:
+      return 6 * blk + 2 * align256(support_bytes(op)) + align256(sizeof(AdaptState));
     default:
       return 0;
   }

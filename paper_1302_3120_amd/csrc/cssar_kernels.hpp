@@ -88,6 +88,7 @@ struct RowArgs {
   // samples delta_j = a + b j; rowc3: azimuth filter turns (A, B), A + B j)
   double c_tau;          // range filter turns per squared range bin, df^2 / (2 K_r)
   int taps;              // truncated sinc length K (even)
+  const unsigned* gate;  // if not NULL, the pass does nothing while *gate == 0
 };
 
 // Column modes.  FWD, INV, A, R: the forward passes.  VB, U, XB: the
@@ -114,6 +115,14 @@ struct AdaptState {
   float sigma2;         // sigma^2, the selected key
   float pad;
   double num;           // ||dX_G||^2 of the current iteration
+  // support-change safeguard of the step
+  double dnum;          // ||F_eta (X+ - X)||^2 = N_a ||X+ - X||^2 of the last threshold pass
+  double c;             // bound constant: omega = (1 - c) ||X+ - X||^2 / ||m o G(X+ - X)||^2
+  double shrink;        // step factor of a shrink, 1 / (kappa (1 - c))
+  unsigned active;      // 1 while this iteration's shrink loop goes on (gates its passes)
+  unsigned changed;     // the threshold pass found supp X+ != supp X
+  unsigned shrinks;     // shrinks taken in this iteration
+  unsigned pad2;
 };
 
 // Marks an unsampled entry of the stored copy of m o y (real part; a NaN
@@ -133,7 +142,11 @@ struct ColArgs {
   const float2* tw;      // w_N^k, N = N_a
   int na, nr;
   int flags;             // FWD: 1 = mask the input and sum |.|^2, 4 = write out2;
-                         // A: 1 = no Xt input, 2 = store X (RM) instead of F_eta X (B4)
+                         // A: 1 = no Xt input, 2 = store X (RM) instead of F_eta X (B4);
+                         // T: 4 = safeguard (support change against supp_old, out2 =
+                         //    F_eta X+ - in1 and its squared norm), 1 = in1 is 0,
+                         //    16 = also store X+ (spatial, row-major) to out3;
+                         // N: 8 = the safeguard's bound test instead of the step
   float scale;           // 1 / N_a (inverse transforms)
   float mu, sigma;       // A: step and threshold lambda*mu
   float* partials;       // per-block partial sums of ||R||^2
@@ -148,6 +161,11 @@ struct ColArgs {
   AdaptState* ad;        // step, threshold, ||dX_G||^2
   uint32_t* supp;        // D (read), T (written): support bits, word tile * CT + thread,
                          // bit k = element (b + T k, tile C + c) of the column tile
+  // support-change safeguard (T with flag 4, N with flag 8)
+  const uint32_t* supp_old;  // T: support bits of the iterate X (compared with X+'s)
+  float2* out3;          // T with flag 16: X+ (spatial, row-major)
+  int* count_out;        // N: shrinks of this iteration (may be NULL)
+  const unsigned* gate;  // if not NULL, the pass does nothing while *gate == 0
 };
 
 // Elementwise work on the E register elements in chunks of CH, with
@@ -374,6 +392,7 @@ __device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane
 
 template <class P, int CJ, bool MID>
 __global__ __launch_bounds__(P::RT) void row_pass_kernel(RowArgs a) {
+  if (a.gate && *a.gate == 0u) return;  // (uniform over the grid)
   __shared__ float2 lds[RowLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
   __shared__ float2 qtab[2 * RowQTab<P>::size];  // double-buffered per unit
@@ -599,6 +618,7 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
 
 template <class P, int CONJ, int KT>
 __global__ __launch_bounds__(P::RT) void row_rda_kernel(RowArgs a) {
+  if (a.gate && *a.gate == 0u) return;  // (uniform over the grid)
   __shared__ float2 lds[RowLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
   load_twiddle_table<P::N>(twl, a.tw);
@@ -803,7 +823,8 @@ __device__ __forceinline__ MaskAddr mask_addr(int b, int j, int T, int nr) {
 template <class P, int MODE, bool PIPE = false, bool SCR = false, bool HT = false>
 __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int c, float2* lds,
                                           const float2* twl, float2 (&pre)[P::E], int next,
-                                          const TwPowers& hp, unsigned* hist0 = nullptr) {
+                                          const TwPowers& hp, unsigned* hist0 = nullptr,
+                                          unsigned* chg = nullptr) {
   constexpr int HSC = HT ? hoisted_pass<P>() : -1;
   constexpr int N = P::N, E = P::E, T = P::T, C = P::C;
   const uint32_t rmb = clamp_bytes((size_t)N * a.nr * 8), b4b = clamp_bytes(b4_bytes(N, a.nr));
@@ -976,8 +997,29 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
       v[k] = cscale(v[k], f);
       w |= (f > 0.0f ? 1u : 0u) << k;
     }
-    a.supp[(uint32_t)tile * P::CT + threadIdx.x] = w;
+    const uint32_t widx = (uint32_t)tile * P::CT + threadIdx.x;
+    a.supp[widx] = w;
+    if (a.flags & 4) {
+      if (w != a.supp_old[widx]) *chg = 1u;
+    }
+    if (a.flags & 16) {
+      const Buf o3(a.out3, rmb);
+      const Addr ar = col_addr(RM, b, j, T, a.nr);
+#pragma unroll
+      for (int k = 0; k < E; ++k) o3.st(v[k], ar.voff, k * ar.kstep);
+    }
     if (!(a.flags & 2)) fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
+    if (a.flags & 4) {
+      // F_eta (X+ - X) and its squared norm (X = 0 with flag 1: an empty
+      // buffer range, every load returns 0)
+      const Buf xo(a.in1, (a.flags & 1) ? 0u : b4b);
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const float2 dk = csub(v[k], xo.f2(ab.voff, k * ab.kstep));
+        acc = fmaf(dk.x, dk.x, fmaf(dk.y, dk.y, acc));
+        out2.st(dk, ab.voff, k * ab.kstep);
+      }
+    }
   } else {  // COL_R: GX = F^-1[W] / N_a; R = m o y - m o GX; out = F R
     fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
     // split plans, screened passes: m o y in chunks of 8 after the transform
@@ -1030,6 +1072,7 @@ struct ColLds {
 template <class P, int MODE, bool SCR>
 __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kernel(ColArgs a) {
   constexpr int C = P::C, CT = P::CT;
+  if (a.gate && *a.gate == 0u) return;  // (uniform over the grid)
   __shared__ float2 lds[ColLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
   __shared__ float red[CT / 64];
@@ -1045,6 +1088,7 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   TwPowers hp;
   if constexpr (HT) hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(b, TwLds{twl, twl + 64});
   float acc = 0.f;
+  unsigned chg = 0u;
   float2 pre[P::E];
   // the value pass (adaptive threshold) also counts the first selection level
   __shared__ unsigned hist0[MODE == COL_V ? 2048 : 1];
@@ -1058,7 +1102,7 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   }
   for (; tile < ntiles; tile += gridDim.x) {
     const int next = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : -1;
-    acc += col_unit<P, MODE, PIPE, SCR, HT>(a, tile, b, c, lds, twl, pre, next, hp, hist0);
+    acc += col_unit<P, MODE, PIPE, SCR, HT>(a, tile, b, c, lds, twl, pre, next, hp, hist0, &chg);
   }
   if constexpr (MODE == COL_V) {
     __syncthreads();
@@ -1074,6 +1118,20 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
     const float part = block_sum<CT>(acc, red);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = part;  // reduced by reduce_partials_kernel
   }
+  if constexpr (MODE == COL_T) {
+    // safeguard: whether the support moved (any block), ||F_eta (X+ - X)||^2,
+    // and the shrink loop goes on only after a support change
+    if (a.flags & 4) {
+      if (__syncthreads_or((int)chg) && threadIdx.x == 0) atomicOr(&a.ad->changed, 1u);
+      const float part = block_sum<CT>(acc, red);
+      double tot;
+      if (last_block_total(part, a.partials, a.counter, gridDim.x, tot) && threadIdx.x == 0) {
+        if (!isfinite(tot)) atomicOr(a.status, 1u);
+        a.ad->dnum = tot;
+        a.ad->active = atomicExch(&a.ad->changed, 0u) ? 1u : 0u;
+      }
+    }
+  }
   if constexpr (MODE == COL_D || MODE == COL_N) {
     // D: ||dX_G||^2; N: ||m o G dX_G||^2 and the step (Section IV.B, eq. (mure)
     // read as the normalized step): mu = ||dX_G||^2 / ||m o G dX_G||^2, and
@@ -1085,10 +1143,26 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
       if (!isfinite(tot)) atomicOr(a.status, 1u);
       if constexpr (MODE == COL_D) {
         a.ad->num = tot;
+      } else if (a.flags & 8) {
+        // the safeguard's bound: omega = (1 - c) ||X+ - X||^2 / ||m o G(X+ - X)||^2
+        // (tot the denominator; no bound when it is 0); a step above it
+        // shrinks by 1 / (kappa (1 - c)) and the loop goes on
+        const double mu = (double)a.ad->mu;
+        const double dn = a.ad->dnum * (double)a.scale;  // ||X+ - X||^2 (Parseval, 1 / N_a)
+        const bool shrink = tot > 0.0 && mu > (1.0 - a.ad->c) * dn / tot;
+        if (shrink) {
+          const float m2 = (float)(mu * a.ad->shrink);
+          a.ad->mu = m2;
+          a.ad->shrinks += 1u;
+          if (a.hist_out) a.hist_out[0] = m2;
+          if (a.count_out) a.count_out[0] = (int)a.ad->shrinks;
+        }
+        a.ad->active = shrink ? 1u : 0u;
       } else {
         const double num = a.ad->num;
         const double mu = (num == 0.0 || !(tot > 0.0)) ? 1.0 : num / tot;
         a.ad->mu = (float)mu;
+        a.ad->shrinks = 0u;
         if (a.hist_out) a.hist_out[0] = (float)mu;
       }
     }

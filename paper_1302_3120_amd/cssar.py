@@ -28,7 +28,7 @@ SYMBOLS = (
     "cssar_batch_set_graph", "cssar_batch_autotune", "cssar_batch_describe",
     "cssar_ita_solve_batched", "cssar_checkpoint_size", "cssar_grad_workspace_size",
     "cssar_ita_forward", "cssar_ita_backward", "cssar_ita_solve_adaptive",
-    "cssar_make_operator_rda", "cssar_operator_chain",
+    "cssar_make_operator_rda", "cssar_operator_chain", "cssar_ita_solve_safeguarded",
 )
 
 PROFILE_KINDS = ("row_M", "row_G", "col_fwd", "col_inv", "col_update_threshold",
@@ -109,6 +109,9 @@ def lib():
         L.cssar_ita_backward.argtypes = [vp, vp, vp, f, i, i, vp, vp, vp, vp, vp, vp]
         L.cssar_ita_solve_adaptive.argtypes = [vp, vp, vp, ctypes.c_long, i, vp, vp, vp, vp, vp, vp]
         L.cssar_ita_solve_adaptive.restype = ctypes.c_int
+        L.cssar_ita_solve_safeguarded.argtypes = [vp, vp, vp, ctypes.c_long, i, ctypes.c_double,
+                                                  ctypes.c_double, i, vp, vp, vp, vp, vp, vp, vp]
+        L.cssar_ita_solve_safeguarded.restype = ctypes.c_int
         L.cssar_ita_forward.restype = ctypes.c_int
         L.cssar_ita_backward.restype = ctypes.c_int
         for name in ("cssar_make_operator", "cssar_destroy_operator", "cssar_apply_G",
@@ -269,6 +272,25 @@ class Operator:
                                               _ptr(out), *(_ptr(h) for h in hists), _ptr(ws),
                                               _stream()))
         return (out, *hists)
+
+    def ita_solve_safeguarded(self, y, mask_bits, k, iters, c=0.01, kappa=2.0, max_shrinks=2,
+                              out=None, ws=None):
+        """ita_solve_adaptive with the support-change safeguard of the step
+        (cssar_ita_solve_safeguarded).  Returns (X^(iters), mu_t, lambda_t,
+        ||R^(t)||^2, shrinks_t), the last four as device tensors of iters
+        entries (float32; int32 for the shrinks)."""
+        y = self._arr(y, "y")
+        if mask_bits.dtype != torch.int32 or not mask_bits.is_cuda:
+            raise TypeError("mask_bits must come from pack_mask")
+        out = torch.empty_like(y) if out is None else self._arr(out, "out")
+        ws = self._ws(ws, 3, y.device)
+        hists = [torch.empty(int(iters), dtype=torch.float32, device=y.device) for _ in range(3)]
+        shrinks = torch.empty(int(iters), dtype=torch.int32, device=y.device)
+        _check(lib().cssar_ita_solve_safeguarded(self._h, _ptr(y), _ptr(mask_bits), int(k), int(iters),
+                                                 float(c), float(kappa), int(max_shrinks), _ptr(out),
+                                                 *(_ptr(h) for h in hists), _ptr(shrinks), _ptr(ws),
+                                                 _stream()))
+        return (out, *hists, shrinks)
 
     def ita_forward(self, y, mask_bits, lam, iters, every, out=None):
         """cssar_ita_forward: X^(iters) and the checkpoint buffer for the

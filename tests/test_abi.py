@@ -105,6 +105,9 @@ def test_null_arguments(L):
     assert L.cssar_ita_solve(None, None, None, 0.1, 10, None, None, None, None) == -1
     assert L.cssar_ita_solve_adaptive(None, None, None, 10, 10, None, None, None, None, None,
                                       None) == -1
+    assert L.cssar_ita_solve_safeguarded(None, None, None, 10, 10, 0.01, 2.0, 2, None, None, None,
+                                         None, None, None, None) == -1
+    assert L.cssar_workspace_size(None, 3) == 0
     assert L.cssar_workspace_size(None, 2) == 0
     assert L.cssar_make_operator_rda(None, 256, 256, 8, ctypes.byref(h)) == -1
     assert L.cssar_make_operator_rda(ctypes.byref(p), 256, 256, 8, None) == -1
