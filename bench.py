@@ -233,6 +233,41 @@ def bench_adaptive(op, y, bits, k, iters, steps, device):
     }
 
 
+def bench_safeguarded(op, y, bits, k, iters, steps, device, c=0.01, kappa=2.0, max_shrinks=2):
+    """The adaptive iteration with the support-change safeguard of its step
+    (cssar_ita_solve_safeguarded: after a support change, the bound
+    (1 - c) ||X+ - X||^2 / ||m o G(X+ - X)||^2 and up to max_shrinks shrinks of
+    the step per iteration) on the headline scene: iterations/s, the shrinks
+    taken and the average duration of each pass kind."""
+    import torch
+    out = torch.empty_like(y)
+    ws = op.workspace(3, device)
+
+    def step():
+        op.ita_solve_safeguarded(y, bits, k, iters, c=c, kappa=kappa, max_shrinks=max_shrinks,
+                                 out=out, ws=ws)
+
+    t = time_steps(step, steps, 1)
+    op.profile(True)
+    op.profile_read()
+    step()
+    prof = op.profile_read()
+    op.profile(False)
+    _, mu, lam, _, shr = op.ita_solve_safeguarded(y, bits, k, iters, c=c, kappa=kappa,
+                                                  max_shrinks=max_shrinks, out=out, ws=ws)
+    shr = shr.cpu()
+    return {
+        "workload": f"the same scene, k = {k}, c = {c}, kappa = {kappa}, at most {max_shrinks} shrinks "
+                    f"per iteration, {iters} iterations per step",
+        "iterations_per_s": steps * iters / t,
+        "shrinks_total": int(shr.sum()),
+        "iterations_with_shrinks": int((shr > 0).sum()),
+        "passes_avg_us": {kind: 1e3 * ms / cnt for kind, (ms, cnt) in prof.items()},
+        "passes_launches": {kind: cnt for kind, (ms, cnt) in prof.items()},
+        "mu_last": float(mu[-1]), "lambda_last": float(lam[-1]),
+    }
+
+
 def bench_rda(shape, y, bits, lam, iters, steps, device):
     """The fixed-parameter iteration with the range-Doppler operator of
     eq. (RDA) (8-tap truncated-sinc migration correction) on the headline
@@ -428,6 +463,8 @@ def main():
                     help="skip the 64-scene batched-versus-plain-loop measurement")
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the adaptive step-and-threshold measurement")
+    ap.add_argument("--no-safeguard", action="store_true",
+                    help="skip the safeguarded adaptive solve measurement")
     ap.add_argument("--no-rda", action="store_true",
                     help="skip the range-Doppler operator measurement")
     ap.add_argument("--no-grad", action="store_true",
@@ -531,6 +568,10 @@ def main():
     if not args.no_adaptive:
         log("bench: adaptive step and threshold")
         rec["adaptive"] = bench_adaptive(op, y, bits, k, args.iters, 3, dev)
+
+    if not args.no_safeguard:
+        log("bench: safeguarded adaptive solve")
+        rec["safeguarded"] = bench_safeguarded(op, y, bits, k, args.iters, 3, dev)
 
     if not args.no_rda:
         log("bench: range-Doppler operator")
