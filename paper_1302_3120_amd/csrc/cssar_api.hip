@@ -138,20 +138,21 @@ int occupancy(const void* fn, int block) {
 #ifndef CSSAR_COL_V2048
 #define CSSAR_COL_V2048 1
 #endif
-// 8192: four-line units through half the LDS (variant 1) for the row passes
-// of the chirp-scaling chain (387 against 527-576 us at 8192 x 8192) and the
-// forward and residual column passes (736 against 949, 498 against 514 us);
-// the update pass keeps the two-column plan (529 against 577 us); 0 keeps
-// variant 0 everywhere.
+// 8192: lines through half the LDS (variant 1) for the row passes of the
+// chirp-scaling chain (two rows per workgroup, two workgroups per CU: 319
+// against 388 us with four rows per workgroup at 8192 x 8192) and the first
+// forward and the inverse column passes (four-column tiles: 738 against 786
+// us); the update and residual passes run variant 0 (two-column tiles, 16
+// elements per thread, 1024 threads: 515 and 478 us against 533 and 503 us
+// with variant 1 for the residual pass and 32 elements per thread for the
+// update pass); 0 keeps variant 0 everywhere.
 #ifndef CSSAR_V8192
 #define CSSAR_V8192 1
 #endif
 int row_variant(int n) { return n == 8192 ? CSSAR_V8192 : 0; }
 int column_variant(int n, int which) {
-  // 8192: the forward, inverse and residual passes on four-column tiles (the
-  // update pass and the passes sharing its support decisions or layout keep
-  // variant 0, which measured faster for them)
-  if (n == 8192) return (which == CK_FWD || which == CK_INV || which == CK_R) ? CSSAR_V8192 : 0;
+  // 8192: the first forward and the inverse passes on four-column tiles
+  if (n == 8192) return (which == CK_FWD || which == CK_INV) ? CSSAR_V8192 : 0;
   if (n == 4096 && which == CK_R) return CSSAR_COL_V4096;
   // (the threshold adjoint recomputes the update pass's V: same plan, same support)
   if (n == 2048 && (which == CK_A || which == CK_VB)) return CSSAR_COL_V2048;

@@ -301,6 +301,9 @@ struct RowLds {
   static constexpr int LI = P::LR >= 4 ? 4 : P::LR;
   static constexpr int LS = LdsSize<LI, P::SPLIT ? P::N / 2 : P::N>::value;  // split: half lines
   static constexpr int size = (P::LR / LI) * LS;
+  // split plans whose LDS lets two workgroups share a CU ask for the
+  // registers that allow it (waves per SIMD)
+  static constexpr int waves_per_eu = (P::SPLIT && size * 8 <= 78 * 1024) ? 2 * (P::RT / 64) / 4 : 1;
 };
 
 // One unit (LR rows) of the row pass of array a:
@@ -391,7 +394,7 @@ __device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane
 #endif
 
 template <class P, int CJ, bool MID>
-__global__ __launch_bounds__(P::RT) void row_pass_kernel(RowArgs a) {
+__global__ __launch_bounds__(P::RT, RowLds<P>::waves_per_eu) void row_pass_kernel(RowArgs a) {
   if (a.gate && *a.gate == 0u) return;  // (uniform over the grid)
   __shared__ float2 lds[RowLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];

@@ -66,9 +66,10 @@ CSSAR_PLAN(2048, 1, 16, 4, 256, 16, 16, 8)
 CSSAR_PLAN(3072, 0, 24, 4, 512, 3, 8, 8, 8, 2)
 CSSAR_PLAN(4096, 0, CSSAR_E4096, CSSAR_C4096, CSSAR_RT4096, 16, 16, 16)
 CSSAR_PLAN(4096, 1, 32, 4, 256, 16, 16, 16)
-CSSAR_PLAN(8192, 0, 32, 2, 256, 16, 16, 16, 2)
-// four-line units of 8192 points through half the LDS (rows and columns)
-CSSAR_PLAN_S(8192, 1, 32, 4, 1024, true, 16, 16, 16, 2)
+CSSAR_PLAN(8192, 0, 16, 2, 512, 16, 16, 16, 2)
+// 8192-point lines through half the LDS: four-column tiles, and two rows per
+// row-pass workgroup (two workgroups per CU)
+CSSAR_PLAN_S(8192, 1, 32, 4, 512, true, 16, 16, 16, 2)
 
 #undef CSSAR_PLAN
 #undef CSSAR_PLAN_S
