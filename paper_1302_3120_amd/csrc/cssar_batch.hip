@@ -222,6 +222,7 @@ int launch_slot(cssar_batch* b, const Group& g, int k, hipStream_t s) {
   ga.start = (const int*)(b->dev_table + sl.start);
   ga.count = (int)g.scenes.size();
   ga.total = sl.total;
+  ga.conj = k == SL_ROW_G ? 1 : 0;  // (the row arguments of the slot carry the same)
   hipError_t e = g.row ? sl.kt->row_group(ga, sl.grid, s) : sl.kt->col_group[col_mode(k)](ga, sl.grid, s);
   if (e != hipSuccess) return fail(CSSAR_EHIP, "grouped launch: %s", hipGetErrorString(e));
   return CSSAR_OK;

@@ -255,6 +255,7 @@ struct GroupArgs {
   const int* start;  // count + 1 prefix sums
   int count;
   int total;         // start[count]
+  int conj;          // row groups: 0 (M) or 1 (G), the same for every array of the launch
 };
 
 // Largest s with start[s] <= u (u is uniform across the workgroup, so the
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(P::RT, RowLds<P>::waves_per_eu) void row_pass_kerne
   }
 }
 
-template <class P>
+template <class P, int CJ>
 __global__ __launch_bounds__(P::RT) void row_group_kernel(GroupArgs g) {
   __shared__ float2 lds[RowLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
@@ -436,7 +437,7 @@ __global__ __launch_bounds__(P::RT) void row_group_kernel(GroupArgs g) {
     const int s = group_find(g.start, g.count, u);
     float2* qt = qtab + par * RowQTab<P>::size;
     if constexpr (TAB) row_qtab_fill<P>(args[s], u - g.start[s], qt);
-    row_unit<P, -1, false, TAB>(args[s], u - g.start[s], ln, lds, twl, hp, qt);
+    row_unit<P, CJ, false, TAB>(args[s], u - g.start[s], ln, lds, twl, hp, qt);
     par ^= 1;
   }
 }
@@ -846,6 +847,26 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
   if constexpr (MODE == COL_A || MODE == COL_VB || MODE == COL_V) {
     // V = F^-1[Xt + mu Z] / N_a
     const float ms = (MODE == COL_V ? a.ad->mu : a.mu) * a.scale;
+    if constexpr (!PIPE) {
+      // both inputs in flight together (all of Z, then all of Xt), combined
+      // once both arrived; on the first iteration Xt is read through an
+      // empty range (every load returns 0, no access).  (Loading Xt only
+      // after Z had arrived cost the batched solver 12 % of its iteration
+      // time.)
+      const Buf x0(a.in0, first ? 0u : b4b);
+      float2 z[E];
+#pragma unroll
+      for (int k = 0; k < E; ++k) z[k] = in1.f2(ai.voff, k * ai.kstep);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < E; ++k) v[k] = x0.f2(ai.voff, k * ai.kstep);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const float2 zs = cscale(z[k], ms);
+        v[k] = first ? zs : make_float2(fmaf(a.scale, v[k].x, zs.x), fmaf(a.scale, v[k].y, zs.y));
+      }
+    } else {
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = cscale(in1.f2(ai.voff, k * ai.kstep), ms);
     if (!first) {
@@ -854,6 +875,7 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
         const float2 x = PIPE ? pre[k] : in0.f2(ai.voff, k * ai.kstep);
         v[k] = make_float2(fmaf(a.scale, x.x, v[k].x), fmaf(a.scale, x.y, v[k].y));
       }
+    }
     }
     if constexpr (PIPE && MODE == COL_A) {
       if (next >= 0) col_preload<P, MODE>(a, next, b, c, pre);
@@ -1218,7 +1240,10 @@ struct Kernels {
     return hipGetLastError();
   }
   static hipError_t row_group(const GroupArgs& g, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(row_group_kernel<P>, dim3(grid), dim3(P::RT), 0, s, g);
+    if (g.conj)
+      hipLaunchKernelGGL((row_group_kernel<P, 1>), dim3(grid), dim3(P::RT), 0, s, g);
+    else
+      hipLaunchKernelGGL((row_group_kernel<P, 0>), dim3(grid), dim3(P::RT), 0, s, g);
     return hipGetLastError();
   }
   // range-Doppler row pass: 8 taps (the default) unrolled, other counts generic

@@ -45,7 +45,7 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_N, false>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_V, false>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_T, false>)},
-      reinterpret_cast<const void*>(&row_group_kernel<P>),
+      reinterpret_cast<const void*>(&row_group_kernel<P, 0>),
       {reinterpret_cast<const void*>(&col_group_kernel<P, COL_FWD>),
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_INV>),
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_A>),
