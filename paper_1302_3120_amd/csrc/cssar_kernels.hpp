@@ -761,9 +761,14 @@ __global__ __launch_bounds__(P::RT) void row_adj_kernel(RowArgs a) {
 #ifndef CSSAR_PIPE_R
 #define CSSAR_PIPE_R 1
 #endif
+#ifndef CSSAR_PIPE_DN
+#define CSSAR_PIPE_DN 1
+#endif
 template <class P, int MODE>
 constexpr bool col_pipelined() {
-  return (MODE == COL_A || (CSSAR_PIPE_R && MODE == COL_R && P::E >= 32 && P::C >= 4)) && !P::SPLIT;
+  return (MODE == COL_A || (CSSAR_PIPE_R && MODE == COL_R && P::E >= 32 && P::C >= 4) ||
+          (CSSAR_PIPE_DN && (MODE == COL_D || MODE == COL_N))) &&
+         !P::SPLIT;
 }
 
 template <class P, int MODE>
@@ -776,7 +781,7 @@ __device__ __forceinline__ void col_preload(const ColArgs& a, int tile, int b, i
     const Buf in0(a.in0, b4b);
 #pragma unroll
     for (int k = 0; k < E; ++k) pre[k] = in0.f2(ab.voff, k * ab.kstep);
-  } else if constexpr (MODE == COL_R) {
+  } else if constexpr (MODE == COL_R || MODE == COL_D || MODE == COL_N) {
     const Buf in0(a.in0, b4b);
 #pragma unroll
     for (int k = 0; k < E; ++k) pre[k] = in0.f2(ab.voff, k * ab.kstep);
@@ -890,6 +895,11 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
   } else {
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = cscale(PIPE ? pre[k] : in0.f2(ai.voff, k * ai.kstep), a.scale);
+    // the single-input adaptive passes load the next tile's input at once
+    // (in flight during both transforms of this one)
+    if constexpr (PIPE && (MODE == COL_D || MODE == COL_N)) {
+      if (next >= 0) col_preload<P, MODE>(a, next, b, c, pre);
+    }
     // (split plans and screened passes load m o y after the inverse
     // transform: registers)
     if constexpr ((MODE == COL_R && !P::SPLIT && !SCR && !HT) || MODE == COL_U) {
