@@ -235,6 +235,7 @@ int cssar_ita_solve_adaptive(cssar_op* op, const void* y, const void* mask_bits,
       r.in0 = P;
       r.out = P;
       if ((rc = launch_col(op, CK_R, r, s))) return rc;
+      if ((rc = residual_total(op, r, t == iters - 1, s))) return rc;  // ||R||^2, non-finite check
     }
     if ((rc = launch_row(op, row_args(op, P, P, 0), s))) return rc;  // P = F_eta dX
     if (t > 0) {
@@ -324,6 +325,7 @@ int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bi
       r.in0 = P;
       r.out = P;
       if ((rc = launch_col(op, CK_R, r, s))) return rc;
+      if ((rc = residual_total(op, r, t == iters - 1, s))) return rc;  // ||R||^2, non-finite check
     }
     if ((rc = launch_row(op, row_args(op, P, P, 0), s))) return rc;  // P = F_eta dX
     if (t > 0) {

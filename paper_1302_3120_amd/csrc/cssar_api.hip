@@ -155,6 +155,10 @@ int column_variant(int n, int which) {
   if (n == 8192) return (which == CK_FWD || which == CK_INV) ? CSSAR_V8192 : 0;
   if (n == 4096 && which == CK_R) return CSSAR_COL_V4096;
   // (the threshold adjoint recomputes the update pass's V: same plan, same support)
+#ifndef CSSAR_COL_R2048
+#define CSSAR_COL_R2048 0
+#endif
+  if (n == 2048 && which == CK_R) return CSSAR_COL_R2048;
   if (n == 2048 && (which == CK_A || which == CK_VB)) return CSSAR_COL_V2048;
   return 0;
 }
@@ -222,6 +226,35 @@ int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s) {
 
 int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
   return timed(op, 2 + which, s, [&] { return op->kcol[which]->col[which](a, op->grid_col[which], s); });
+}
+
+// ||R||^2 of the residual pass from its per-block partials (FP64, in the
+// order of the last-block reduction of the other passes), into out (if not
+// NULL), and bit 0 of status when it is not finite.
+__global__ __launch_bounds__(256) void residual_total_kernel(const float* __restrict__ part, int nblocks,
+                                                             float* out, unsigned* status) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += 256) acc += (double)part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double t = sh[0];
+    if (out) out[0] = (float)t;
+    if (!isfinite(t)) atomicOr(status, 1u);
+  }
+}
+
+int residual_total(cssar_op* op, const ColArgs& a, bool check, hipStream_t s) {
+  if (!(check || a.hist_out)) return CSSAR_OK;
+  hipLaunchKernelGGL(residual_total_kernel, dim3(1), dim3(256), 0, s, (const float*)a.partials,
+                     op->grid_col[CK_R], a.hist_out, a.status);
+  HIP_TRY(hipGetLastError());
+  return CSSAR_OK;
 }
 
 int launch_row_mid(cssar_op* op, const RowArgs& a, hipStream_t s) {
@@ -492,6 +525,7 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
       r.in0 = P;
       r.out = P;
       if ((rc = col(CK_R, r))) return rc;
+      if ((rc = residual_total(op, r, last, s))) return rc;  // (the last one: non-finite check)
     }
     // P = F_eta M R (row chain of M)
     if ((rc = row(row_args(op, P, P, 0)))) return rc;

@@ -153,6 +153,7 @@ int forward_iteration(cssar_op* op, int t, const float2* Xt, float2* P, float2* 
     r.in0 = P;
     r.out = P;
     if ((rc = launch_col(op, CK_R, r, s))) return rc;
+    if ((rc = residual_total(op, r, rm_out, s))) return rc;  // (last iteration: non-finite check)
   }
   if ((rc = launch_row(op, row_args(op, P, P, 0), s))) return rc;
   ColArgs u = a;

@@ -106,6 +106,9 @@ inline int timed(cssar_op* op, int kind, hipStream_t s, F&& launch) {
 // Launch a pass kernel of the operator (timed when profiling is on).
 int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s);
 int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s);
+// After a residual pass: ||R||^2 into a.hist_out (if not NULL) and the
+// non-finite check (if check or a.hist_out).
+int residual_total(cssar_op* op, const ColArgs& a, bool check, hipStream_t s);
 int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s);
 int launch_row_mid(cssar_op* op, const RowArgs& a, hipStream_t s);
 int launch_col_scr(cssar_op* op, int which, const ColArgs& a, hipStream_t s);

@@ -1118,7 +1118,10 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   const int ntiles = a.nr / C;  // N_r is a multiple of C
   // the update and residual passes take the second pass's twiddles from
   // registers (computed once here) instead of the prefetch
-  constexpr bool HT = (MODE == COL_A || MODE == COL_R) && hoisted_pass<P>() >= 0 && !P::SPLIT;
+#ifndef CSSAR_R_HT
+#define CSSAR_R_HT 1
+#endif
+  constexpr bool HT = (MODE == COL_A || (MODE == COL_R && CSSAR_R_HT)) && hoisted_pass<P>() >= 0 && !P::SPLIT;
   constexpr bool PIPE = col_pipelined<P, MODE>() && !SCR && !HT;
   TwPowers hp;
   if constexpr (HT) hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(b, TwLds{twl, twl + 64});
@@ -1144,8 +1147,15 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
     for (int i = threadIdx.x; i < 2048; i += CT)
       if (hist0[i]) atomicAdd(&a.ad->hist[i], hist0[i]);
   }
-  const bool want_norm = (MODE == COL_R) || (MODE == COL_FWD && (a.flags & 1));
-  if (want_norm) {
+  if constexpr (MODE == COL_R) {
+    // ||R||^2: one partial per block, summed by a one-block kernel launched
+    // after this pass (a last-block reduction here would need a device-scope
+    // fence per block, which writes back the L2 and waits for this block's
+    // stores: 13 us of a 102 us pass at 4096 x 4096)
+    const float part = block_sum<CT>(acc, red);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = part;
+  }
+  if (MODE == COL_FWD && (a.flags & 1)) {
     const float part = block_sum<CT>(acc, red);
     finish_partials(part, a.partials, a.counter, a.hist_out, a.status, gridDim.x);
   }
@@ -1217,7 +1227,10 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_group_kern
   const int b = threadIdx.x / C;
   float2 pre[P::E];
   // same per-line arithmetic as the single-array kernel (bit-identical results)
-  constexpr bool HT = (MODE == COL_A || MODE == COL_R) && hoisted_pass<P>() >= 0 && !P::SPLIT;
+#ifndef CSSAR_R_HT
+#define CSSAR_R_HT 1
+#endif
+  constexpr bool HT = (MODE == COL_A || (MODE == COL_R && CSSAR_R_HT)) && hoisted_pass<P>() >= 0 && !P::SPLIT;
   TwPowers hp;
   if constexpr (HT) hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(b, TwLds{twl, twl + 64});
   for (int u = xcd_logical_block(); u < g.total; u += gridDim.x) {
