@@ -157,6 +157,43 @@ __global__ void adapt_init_kernel(AdaptState* st, unsigned k1, float* mu0, doubl
   }
 }
 
+// Totals of the restricted-step pass D (||dX_G||^2 into num) and of the
+// safeguarded threshold pass T (||F_eta (X+ - X)||^2 into dnum; the shrink
+// loop goes on after a support change) from their per-block partials, in
+// the order of the last-block reductions; bit 0 of status if not finite.
+__global__ __launch_bounds__(256) void adapt_total_kernel(const float* __restrict__ part, int nblocks,
+                                                          AdaptState* st, int which, unsigned* status,
+                                                          const unsigned* gate) {
+  if (gate && *gate == 0u) return;
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += 256) acc += (double)part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double t = sh[0];
+    if (!isfinite(t)) atomicOr(status, 1u);
+    if (which == 0) {
+      st->num = t;
+    } else {
+      st->dnum = t;
+      st->active = st->changed ? 1u : 0u;
+      st->changed = 0u;
+    }
+  }
+}
+
+int adapt_total(cssar_op* op, int ck, AdaptState* st, const unsigned* gate, hipStream_t s) {
+  hipLaunchKernelGGL(adapt_total_kernel, dim3(1), dim3(256), 0, s, (const float*)op->partials, op->grid_col[ck],
+                     st, ck == CK_D ? 0 : 1, op->counter + 1, gate);
+  HIP_TRY(hipGetLastError());
+  return CSSAR_OK;
+}
+
 // Zero n 32-bit words (a kernel rather than a memset node, so the solve can
 // be captured in a graph).
 __global__ void zero_words_kernel(uint32_t* p, size_t n) {
@@ -244,6 +281,7 @@ int cssar_ita_solve_adaptive(cssar_op* op, const void* y, const void* mask_bits,
       d.out = Q;
       d.hist_out = nullptr;
       if ((rc = launch_col(op, CK_D, d, s))) return rc;
+      if ((rc = adapt_total(op, CK_D, st, nullptr, s))) return rc;
       if ((rc = launch_row(op, row_args(op, Q, Q, 1), s))) return rc;
       ColArgs m = a;  // mu = ||dX_G||^2 / ||m o G dX_G||^2
       m.in0 = Q;
@@ -334,6 +372,7 @@ int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bi
       d.out = Q;
       d.hist_out = nullptr;
       if ((rc = launch_col(op, CK_D, d, s))) return rc;
+      if ((rc = adapt_total(op, CK_D, st, nullptr, s))) return rc;
       if ((rc = launch_row(op, row_args(op, Q, Q, 1), s))) return rc;
       ColArgs m = a;  // mu = ||dX_G||^2 / ||m o G dX_G||^2; no shrinks yet
       m.in0 = Q;
@@ -365,6 +404,7 @@ int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bi
       x.hist_out = nullptr;
       x.gate = gate;
       if ((rc = launch_col(op, CK_T, x, s))) return rc;
+      if ((rc = adapt_total(op, CK_T, st, gate, s))) return rc;
       if (round == max_shrinks) break;
       RowArgs g = row_args(op, Df, Df, 1);  // F_eta G(X+ - X), after a support change
       g.gate = active;

@@ -1166,29 +1166,31 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   if constexpr (MODE == COL_T) {
     // safeguard: whether the support moved (any block), ||F_eta (X+ - X)||^2,
     // and the shrink loop goes on only after a support change
+    // (per-block partials and the change flag; a one-block kernel after this
+    // pass forms the total and the flag, see the residual pass)
     if (a.flags & 4) {
       if (__syncthreads_or((int)chg) && threadIdx.x == 0) atomicOr(&a.ad->changed, 1u);
       const float part = block_sum<CT>(acc, red);
-      double tot;
-      if (last_block_total(part, a.partials, a.counter, gridDim.x, tot) && threadIdx.x == 0) {
-        if (!isfinite(tot)) atomicOr(a.status, 1u);
-        a.ad->dnum = tot;
-        a.ad->active = atomicExch(&a.ad->changed, 0u) ? 1u : 0u;
-      }
+      if (threadIdx.x == 0) a.partials[blockIdx.x] = part;
     }
   }
-  if constexpr (MODE == COL_D || MODE == COL_N) {
-    // D: ||dX_G||^2; N: ||m o G dX_G||^2 and the step (Section IV.B, eq. (mure)
-    // read as the normalized step): mu = ||dX_G||^2 / ||m o G dX_G||^2, and
-    // mu = 1 when either is 0 (empty support: the same ratio over the whole
-    // image is 1 because G M = I and M is unitary)
+  if constexpr (MODE == COL_D) {
+    // ||dX_G||^2: per-block partials, totalled by a one-block kernel after
+    // this pass (as for the residual pass: this pass writes a whole array)
+    const float part = block_sum<CT>(acc, red);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = part;
+  }
+  if constexpr (MODE == COL_N) {
+    // ||m o G dX_G||^2 and the step (Section IV.B, eq. (mure) read as the
+    // normalized step): mu = ||dX_G||^2 / ||m o G dX_G||^2, and mu = 1 when
+    // either is 0 (empty support: the same ratio over the whole image is 1
+    // because G M = I and M is unitary).  This pass writes no array, so its
+    // last-block reduction is cheap.
     const float part = block_sum<CT>(acc, red);
     double tot;
     if (last_block_total(part, a.partials, a.counter, gridDim.x, tot) && threadIdx.x == 0) {
       if (!isfinite(tot)) atomicOr(a.status, 1u);
-      if constexpr (MODE == COL_D) {
-        a.ad->num = tot;
-      } else if (a.flags & 8) {
+      if (a.flags & 8) {
         // the safeguard's bound: omega = (1 - c) ||X+ - X||^2 / ||m o G(X+ - X)||^2
         // (tot the denominator; no bound when it is 0); a step above it
         // shrinks by 1 / (kappa (1 - c)) and the loop goes on
