@@ -157,13 +157,26 @@ __global__ void adapt_init_kernel(AdaptState* st, unsigned k1, float* mu0, doubl
   }
 }
 
-// Totals of the restricted-step pass D (||dX_G||^2 into num) and of the
-// safeguarded threshold pass T (||F_eta (X+ - X)||^2 into dnum; the shrink
-// loop goes on after a support change) from their per-block partials, in
-// the order of the last-block reductions; bit 0 of status if not finite.
+// What the one-block kernel after a pass does with the pass's total.
+enum AdaptTotal { AT_NUM = 0, AT_CHANGE, AT_STEP, AT_BOUND };
+
+// Totals of the passes of the adaptive iteration from their per-block
+// partials (summed in the order of the last-block reductions; bit 0 of
+// status if not finite), and what follows from them:
+//   AT_NUM    (pass D): ||dX_G||^2 into num;
+//   AT_CHANGE (pass T, safeguard): ||F_eta (X+ - X)||^2 into dnum; the shrink
+//             loop goes on after a support change;
+//   AT_STEP   (pass N): the step of Section IV.B (eq. (mure) read as the
+//             normalized step) mu = ||dX_G||^2 / ||m o G dX_G||^2, and mu = 1
+//             when either is 0 (empty support: the same ratio over the whole
+//             image is 1 because G M = I and M is unitary);
+//   AT_BOUND  (pass N, safeguard): omega = (1 - c) ||X+ - X||^2 /
+//             ||m o G(X+ - X)||^2 (no bound when the denominator is 0); a
+//             step above it shrinks by 1 / (kappa (1 - c)) and the loop goes on.
 __global__ __launch_bounds__(256) void adapt_total_kernel(const float* __restrict__ part, int nblocks,
                                                           AdaptState* st, int which, unsigned* status,
-                                                          const unsigned* gate) {
+                                                          const unsigned* gate, double inv_na,
+                                                          float* mu_out, int* count_out) {
   if (gate && *gate == 0u) return;
   __shared__ double sh[256];
   double acc = 0.0;
@@ -177,19 +190,38 @@ __global__ __launch_bounds__(256) void adapt_total_kernel(const float* __restric
   if (threadIdx.x == 0) {
     const double t = sh[0];
     if (!isfinite(t)) atomicOr(status, 1u);
-    if (which == 0) {
+    if (which == AT_NUM) {
       st->num = t;
-    } else {
+    } else if (which == AT_CHANGE) {
       st->dnum = t;
       st->active = st->changed ? 1u : 0u;
       st->changed = 0u;
+    } else if (which == AT_STEP) {
+      const double num = st->num;
+      const double mu = (num == 0.0 || !(t > 0.0)) ? 1.0 : num / t;
+      st->mu = (float)mu;
+      st->shrinks = 0u;
+      if (mu_out) mu_out[0] = (float)mu;
+    } else {
+      const double mu = (double)st->mu;
+      const double dn = st->dnum * inv_na;  // ||X+ - X||^2 (Parseval)
+      const bool shrink = t > 0.0 && mu > (1.0 - st->c) * dn / t;
+      if (shrink) {
+        const float m2 = (float)(mu * st->shrink);
+        st->mu = m2;
+        st->shrinks += 1u;
+        if (mu_out) mu_out[0] = m2;
+        if (count_out) count_out[0] = (int)st->shrinks;
+      }
+      st->active = shrink ? 1u : 0u;
     }
   }
 }
 
-int adapt_total(cssar_op* op, int ck, AdaptState* st, const unsigned* gate, hipStream_t s) {
+int adapt_total(cssar_op* op, int ck, int which, AdaptState* st, const unsigned* gate, float* mu_out,
+                int* count_out, hipStream_t s) {
   hipLaunchKernelGGL(adapt_total_kernel, dim3(1), dim3(256), 0, s, (const float*)op->partials, op->grid_col[ck],
-                     st, ck == CK_D ? 0 : 1, op->counter + 1, gate);
+                     st, which, op->counter + 1, gate, 1.0 / op->na, mu_out, count_out);
   HIP_TRY(hipGetLastError());
   return CSSAR_OK;
 }
@@ -281,12 +313,14 @@ int cssar_ita_solve_adaptive(cssar_op* op, const void* y, const void* mask_bits,
       d.out = Q;
       d.hist_out = nullptr;
       if ((rc = launch_col(op, CK_D, d, s))) return rc;
-      if ((rc = adapt_total(op, CK_D, st, nullptr, s))) return rc;
+      if ((rc = adapt_total(op, CK_D, AT_NUM, st, nullptr, nullptr, nullptr, s))) return rc;
       if ((rc = launch_row(op, row_args(op, Q, Q, 1), s))) return rc;
       ColArgs m = a;  // mu = ||dX_G||^2 / ||m o G dX_G||^2
       m.in0 = Q;
-      m.hist_out = mu_hist ? mu_hist + t : nullptr;
+      m.hist_out = nullptr;
       if ((rc = launch_col(op, CK_N, m, s))) return rc;
+      if ((rc = adapt_total(op, CK_N, AT_STEP, st, nullptr, mu_hist ? mu_hist + t : nullptr, nullptr, s)))
+        return rc;
     }
     ColArgs v = a;  // V = X + mu dX (spatial, into P)
     v.in0 = X;
@@ -372,12 +406,14 @@ int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bi
       d.out = Q;
       d.hist_out = nullptr;
       if ((rc = launch_col(op, CK_D, d, s))) return rc;
-      if ((rc = adapt_total(op, CK_D, st, nullptr, s))) return rc;
+      if ((rc = adapt_total(op, CK_D, AT_NUM, st, nullptr, nullptr, nullptr, s))) return rc;
       if ((rc = launch_row(op, row_args(op, Q, Q, 1), s))) return rc;
       ColArgs m = a;  // mu = ||dX_G||^2 / ||m o G dX_G||^2; no shrinks yet
       m.in0 = Q;
-      m.hist_out = mu_hist ? mu_hist + t : nullptr;
+      m.hist_out = nullptr;
       if ((rc = launch_col(op, CK_N, m, s))) return rc;
+      if ((rc = adapt_total(op, CK_N, AT_STEP, st, nullptr, mu_hist ? mu_hist + t : nullptr, nullptr, s)))
+        return rc;
     }
     // The step, then up to max_shrinks rounds that run only while the
     // previous round moved the support and its step exceeded the bound.
@@ -404,18 +440,19 @@ int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bi
       x.hist_out = nullptr;
       x.gate = gate;
       if ((rc = launch_col(op, CK_T, x, s))) return rc;
-      if ((rc = adapt_total(op, CK_T, st, gate, s))) return rc;
+      if ((rc = adapt_total(op, CK_T, AT_CHANGE, st, gate, nullptr, nullptr, s))) return rc;
       if (round == max_shrinks) break;
       RowArgs g = row_args(op, Df, Df, 1);  // F_eta G(X+ - X), after a support change
       g.gate = active;
       if ((rc = launch_row(op, g, s))) return rc;
       ColArgs b = a;  // the bound; shrink mu or end the loop
       b.in0 = Df;
-      b.flags = 8;
-      b.hist_out = mu_hist ? mu_hist + t : nullptr;
-      b.count_out = shrink_hist ? shrink_hist + t : nullptr;
+      b.hist_out = nullptr;
       b.gate = active;
       if ((rc = launch_col(op, CK_N, b, s))) return rc;
+      if ((rc = adapt_total(op, CK_N, AT_BOUND, st, active, mu_hist ? mu_hist + t : nullptr,
+                            shrink_hist ? shrink_hist + t : nullptr, s)))
+        return rc;
     }
     std::swap(X, Xn);
     std::swap(so, sn);

@@ -145,8 +145,7 @@ struct ColArgs {
                          // A: 1 = no Xt input, 2 = store X (RM) instead of F_eta X (B4);
                          // T: 4 = safeguard (support change against supp_old, out2 =
                          //    F_eta X+ - in1 and its squared norm), 1 = in1 is 0,
-                         //    16 = also store X+ (spatial, row-major) to out3;
-                         // N: 8 = the safeguard's bound test instead of the step
+                         //    16 = also store X+ (spatial, row-major) to out3
   float scale;           // 1 / N_a (inverse transforms)
   float mu, sigma;       // A: step and threshold lambda*mu
   float* partials;       // per-block partial sums of ||R||^2
@@ -161,10 +160,9 @@ struct ColArgs {
   AdaptState* ad;        // step, threshold, ||dX_G||^2
   uint32_t* supp;        // D (read), T (written): support bits, word tile * CT + thread,
                          // bit k = element (b + T k, tile C + c) of the column tile
-  // support-change safeguard (T with flag 4, N with flag 8)
+  // support-change safeguard (T with flag 4)
   const uint32_t* supp_old;  // T: support bits of the iterate X (compared with X+'s)
   float2* out3;          // T with flag 16: X+ (spatial, row-major)
-  int* count_out;        // N: shrinks of this iteration (may be NULL)
   const unsigned* gate;  // if not NULL, the pass does nothing while *gate == 0
 };
 
@@ -1181,38 +1179,11 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
     if (threadIdx.x == 0) a.partials[blockIdx.x] = part;
   }
   if constexpr (MODE == COL_N) {
-    // ||m o G dX_G||^2 and the step (Section IV.B, eq. (mure) read as the
-    // normalized step): mu = ||dX_G||^2 / ||m o G dX_G||^2, and mu = 1 when
-    // either is 0 (empty support: the same ratio over the whole image is 1
-    // because G M = I and M is unitary).  This pass writes no array, so its
-    // last-block reduction is cheap.
+    // ||m o G dX_G||^2 (or ||m o G(X+ - X)||^2 for the safeguard's bound):
+    // per-block partials; the step or the bound test follow in a one-block
+    // kernel after this pass
     const float part = block_sum<CT>(acc, red);
-    double tot;
-    if (last_block_total(part, a.partials, a.counter, gridDim.x, tot) && threadIdx.x == 0) {
-      if (!isfinite(tot)) atomicOr(a.status, 1u);
-      if (a.flags & 8) {
-        // the safeguard's bound: omega = (1 - c) ||X+ - X||^2 / ||m o G(X+ - X)||^2
-        // (tot the denominator; no bound when it is 0); a step above it
-        // shrinks by 1 / (kappa (1 - c)) and the loop goes on
-        const double mu = (double)a.ad->mu;
-        const double dn = a.ad->dnum * (double)a.scale;  // ||X+ - X||^2 (Parseval, 1 / N_a)
-        const bool shrink = tot > 0.0 && mu > (1.0 - a.ad->c) * dn / tot;
-        if (shrink) {
-          const float m2 = (float)(mu * a.ad->shrink);
-          a.ad->mu = m2;
-          a.ad->shrinks += 1u;
-          if (a.hist_out) a.hist_out[0] = m2;
-          if (a.count_out) a.count_out[0] = (int)a.ad->shrinks;
-        }
-        a.ad->active = shrink ? 1u : 0u;
-      } else {
-        const double num = a.ad->num;
-        const double mu = (num == 0.0 || !(tot > 0.0)) ? 1.0 : num / tot;
-        a.ad->mu = (float)mu;
-        a.ad->shrinks = 0u;
-        if (a.hist_out) a.hist_out[0] = (float)mu;
-      }
-    }
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = part;
   }
 }
 
