@@ -298,13 +298,14 @@ int cssar_ita_solve_adaptive(cssar_op* op, const void* y, const void* mask_bits,
       f.out2 = Y;
       f.flags = 1 | 4;
       if ((rc = launch_col(op, CK_FWD, f, s))) return rc;
+      if ((rc = residual_total(op, CK_FWD, f, true, s))) return rc;
     } else {
       if ((rc = launch_row(op, row_args(op, X, P, 1), s))) return rc;
       ColArgs r = a;
       r.in0 = P;
       r.out = P;
       if ((rc = launch_col(op, CK_R, r, s))) return rc;
-      if ((rc = residual_total(op, r, t == iters - 1, s))) return rc;  // ||R||^2, non-finite check
+      if ((rc = residual_total(op, CK_R, r, t == iters - 1, s))) return rc;  // ||R||^2, non-finite check
     }
     if ((rc = launch_row(op, row_args(op, P, P, 0), s))) return rc;  // P = F_eta dX
     if (t > 0) {
@@ -391,13 +392,14 @@ int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bi
       f.out2 = Y;
       f.flags = 1 | 4;
       if ((rc = launch_col(op, CK_FWD, f, s))) return rc;
+      if ((rc = residual_total(op, CK_FWD, f, true, s))) return rc;
     } else {
       if ((rc = launch_row(op, row_args(op, X, P, 1), s))) return rc;
       ColArgs r = a;
       r.in0 = P;
       r.out = P;
       if ((rc = launch_col(op, CK_R, r, s))) return rc;
-      if ((rc = residual_total(op, r, t == iters - 1, s))) return rc;  // ||R||^2, non-finite check
+      if ((rc = residual_total(op, CK_R, r, t == iters - 1, s))) return rc;  // ||R||^2, non-finite check
     }
     if ((rc = launch_row(op, row_args(op, P, P, 0), s))) return rc;  // P = F_eta dX
     if (t > 0) {

@@ -177,7 +177,6 @@ ColArgs col_args(const cssar_op* op) {
   a.scale = 1.0f / (float)op->na;
   a.mu = 1.0f;
   a.partials = op->partials;
-  a.counter = op->counter;
   a.status = op->counter + 1;
   a.rowc1 = op->rowc1;
   a.rowc3 = op->rowc3;
@@ -228,7 +227,8 @@ int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
   return timed(op, 2 + which, s, [&] { return op->kcol[which]->col[which](a, op->grid_col[which], s); });
 }
 
-// ||R||^2 of the residual pass from its per-block partials (FP64, in the
+// ||R||^2 of the residual pass (or ||m o y||^2 of the first forward pass)
+// from its per-block partials (FP64, in the
 // order of the last-block reduction of the other passes), into out (if not
 // NULL), and bit 0 of status when it is not finite.
 __global__ __launch_bounds__(256) void residual_total_kernel(const float* __restrict__ part, int nblocks,
@@ -249,10 +249,10 @@ __global__ __launch_bounds__(256) void residual_total_kernel(const float* __rest
   }
 }
 
-int residual_total(cssar_op* op, const ColArgs& a, bool check, hipStream_t s) {
+int residual_total(cssar_op* op, int ck, const ColArgs& a, bool check, hipStream_t s) {
   if (!(check || a.hist_out)) return CSSAR_OK;
   hipLaunchKernelGGL(residual_total_kernel, dim3(1), dim3(256), 0, s, (const float*)a.partials,
-                     op->grid_col[CK_R], a.hist_out, a.status);
+                     op->grid_col[ck], a.hist_out, a.status);
   HIP_TRY(hipGetLastError());
   return CSSAR_OK;
 }
@@ -518,6 +518,7 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
       f.out2 = Y;
       f.flags = 1 | 4;
       if ((rc = col(CK_FWD, f))) return rc;
+      if ((rc = residual_total(op, CK_FWD, f, true, s))) return rc;
     } else {
       // P = F_eta G X (row chain of G on Xt); then R = m o y - m o G X, P = F_eta R
       if ((rc = row(row_args(op, X, P, 1)))) return rc;
@@ -525,7 +526,7 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
       r.in0 = P;
       r.out = P;
       if ((rc = col(CK_R, r))) return rc;
-      if ((rc = residual_total(op, r, last, s))) return rc;  // (the last one: non-finite check)
+      if ((rc = residual_total(op, CK_R, r, last, s))) return rc;  // (the last one: non-finite check)
     }
     // P = F_eta M R (row chain of M)
     if ((rc = row(row_args(op, P, P, 0)))) return rc;

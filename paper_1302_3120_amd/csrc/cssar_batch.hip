@@ -176,7 +176,6 @@ int upload_tables(cssar_batch* b, const CallArgs& c, hipStream_t s) {
         }
         ColArgs a = col_args(op);
         a.partials = nullptr;
-        a.counter = nullptr;
         a.status = nullptr;
         a.hist_out = nullptr;
         a.y = Y;

@@ -503,50 +503,4 @@ __device__ __forceinline__ float block_sum(float x, float* red) {
   return s;
 }
 
-// Last-block-done reduction of one float per block: every block stores its
-// partial; the block that finishes last sums them in FP64 in a fixed order
-// (thread t takes partials t, t + 256, ... in order, then a fixed tree) and
-// returns true with the total in total (the same in all its threads); the
-// others return false.  counter is reset for the next use.
-__device__ __forceinline__ bool last_block_total(float part, float* partials, unsigned* counter,
-                                                 int nblocks, double& total) {
-  __shared__ int is_last;
-  __shared__ double sh[256];
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = part;
-    __threadfence();
-    unsigned done = atomicAdd(counter, 1u);
-    is_last = (done == (unsigned)(nblocks - 1));
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  // (slots are strided over the threads, so any block size works)
-  for (int t = threadIdx.x; t < 256; t += blockDim.x) {
-    double s = 0.0;
-    for (int i = t; i < nblocks; i += 256) s += (double)partials[i];
-    sh[t] = s;
-  }
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    for (int t = threadIdx.x; t < w; t += blockDim.x) sh[t] += sh[t + w];
-    __syncthreads();
-  }
-  total = sh[0];
-  if (threadIdx.x == 0) atomicExch(counter, 0u);
-  return true;
-}
-
-// The total of last_block_total into out[0] (if out is not NULL); sets bit 0
-// of status when it is not finite.
-__device__ __forceinline__ void finish_partials(float part, float* partials, unsigned* counter,
-                                                float* out, unsigned* status, int nblocks) {
-  double s;
-  if (!last_block_total(part, partials, counter, nblocks, s)) return;
-  if (threadIdx.x == 0) {
-    if (out) out[0] = (float)s;
-    if (!isfinite(s)) atomicOr(status, 1u);
-  }
-}
-
 }  // namespace cssar

@@ -147,13 +147,14 @@ int forward_iteration(cssar_op* op, int t, const float2* Xt, float2* P, float2* 
     f.out2 = Y;
     f.flags = 1 | 4;
     if ((rc = launch_col(op, CK_FWD, f, s))) return rc;
+    if ((rc = residual_total(op, CK_FWD, f, true, s))) return rc;  // (non-finite check)
   } else {
     if ((rc = launch_row(op, row_args(op, Xt, P, 1), s))) return rc;
     ColArgs r = a;
     r.in0 = P;
     r.out = P;
     if ((rc = launch_col(op, CK_R, r, s))) return rc;
-    if ((rc = residual_total(op, r, rm_out, s))) return rc;  // (last iteration: non-finite check)
+    if ((rc = residual_total(op, CK_R, r, rm_out, s))) return rc;  // (last iteration: non-finite check)
   }
   if ((rc = launch_row(op, row_args(op, P, P, 0), s))) return rc;
   ColArgs u = a;

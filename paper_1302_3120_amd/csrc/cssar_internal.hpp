@@ -58,7 +58,7 @@ struct cssar_op {
   float2* tw_a = nullptr;           // w_{N_a}^k
   float2* tw_r = nullptr;           // w_{N_r}^k
   float* partials = nullptr;        // per-block partial sums
-  unsigned* counter = nullptr;      // [0] last-block counter, [1] status bits
+  unsigned* counter = nullptr;      // [1]: status bits (non-finite norms); [0] unused
   float* rowd = nullptr;            // per Doppler bin: 18 screen-derivative coefficients
   int grid_row = 0;
   int grid_rda = 0;
@@ -106,9 +106,10 @@ inline int timed(cssar_op* op, int kind, hipStream_t s, F&& launch) {
 // Launch a pass kernel of the operator (timed when profiling is on).
 int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s);
 int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s);
-// After a residual pass: ||R||^2 into a.hist_out (if not NULL) and the
-// non-finite check (if check or a.hist_out).
-int residual_total(cssar_op* op, const ColArgs& a, bool check, hipStream_t s);
+// After a residual pass (ck = CK_R) or the first, masked forward pass
+// (CK_FWD): ||R||^2 into a.hist_out (if not NULL) and the non-finite check
+// (if check or a.hist_out).
+int residual_total(cssar_op* op, int ck, const ColArgs& a, bool check, hipStream_t s);
 int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s);
 int launch_row_mid(cssar_op* op, const RowArgs& a, hipStream_t s);
 int launch_col_scr(cssar_op* op, int which, const ColArgs& a, hipStream_t s);

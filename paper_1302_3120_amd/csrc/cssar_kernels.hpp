@@ -149,7 +149,6 @@ struct ColArgs {
   float scale;           // 1 / N_a (inverse transforms)
   float mu, sigma;       // A: step and threshold lambda*mu
   float* partials;       // per-block partial sums of ||R||^2
-  unsigned* counter;     // last-block detection
   float* hist_out;       // where the total ||R||^2 goes (may be NULL)
   unsigned* status;      // bit 0: non-finite residual
   // screened column passes (range-Doppler screens moved out of the row passes)
@@ -1153,9 +1152,9 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
     const float part = block_sum<CT>(acc, red);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = part;
   }
-  if (MODE == COL_FWD && (a.flags & 1)) {
+  if (MODE == COL_FWD && (a.flags & 1)) {  // ||m o y||^2 (the first residual), as for R
     const float part = block_sum<CT>(acc, red);
-    finish_partials(part, a.partials, a.counter, a.hist_out, a.status, gridDim.x);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = part;
   }
   if constexpr (MODE == COL_VB) {
     const float part = block_sum<CT>(acc, red);
