@@ -148,9 +148,10 @@ struct ColArgs {
                          //    16 = also store X+ (spatial, row-major) to out3
   float scale;           // 1 / N_a (inverse transforms)
   float mu, sigma;       // A: step and threshold lambda*mu
-  float* partials;       // per-block partial sums of ||R||^2
-  float* hist_out;       // where the total ||R||^2 goes (may be NULL)
-  unsigned* status;      // bit 0: non-finite residual
+  float* partials;       // per-block partial sums (R, masked FWD, D, N, safeguarded T)
+  float* hist_out;       // R, masked FWD: where the total ||R||^2 goes (may be NULL; the
+                         // passes write per-block partials, a one-block kernel the total)
+  unsigned* status;      // bit 0: non-finite norm (set by the one-block total kernels)
   // screened column passes (range-Doppler screens moved out of the row passes)
   const double2* rowc1;  // per Doppler bin: Phi1 (a1, d1)
   const double2* rowc3;  //                  Phi3 (D, b3)
