@@ -41,14 +41,17 @@ KIND_SYMBOL = {
     "row_G": "row_pass_kernel<cssar::Plan<{n}, 0>, 1, false>",
     "col_fwd": "col_pass_kernel<cssar::Plan<{n}, 0>, 0, false>",
     "col_inv": "col_pass_kernel<cssar::Plan<{n}, 0>, 1, false>",
-    "col_update_threshold": "col_pass_kernel<cssar::Plan<{n}, 0>, 2, false>",
+    "col_update_threshold": "col_pass_kernel<cssar::Plan<{n}, {v}>, 2, false>",
     "col_residual": "col_pass_kernel<cssar::Plan<{n}, {v}>, 3, false>",
 }
+# plan variant of a pass kind at a line length, where it is not 0 (the
+# library's column_variant for the 4096-point passes)
+KIND_VARIANT = {("col_residual", 4096): 1, ("col_update_threshold", 4096): 2}
 
 
 def kind_symbol(kind, n):
     """Kernel symbol of a pass kind at line length n."""
-    return KIND_SYMBOL[kind].format(n=n, v=1 if (kind == "col_residual" and n == 4096) else 0)
+    return KIND_SYMBOL[kind].format(n=n, v=KIND_VARIANT.get((kind, n), 0))
 # Counter-based HBM bytes per dispatch, written by --rocprof-summary from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and a copy-kernel calibration.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ita_passes_sparse_4096.md")

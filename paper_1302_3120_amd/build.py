@@ -21,7 +21,9 @@ LIB = os.path.join(HERE, "libcssar.so")
 LENGTHS = (64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096, 8192)
 # (length, variant) pairs: every length has variant 0; these also have 1
 VARIANT1 = (512, 1024, 1536, 2048, 4096, 8192)
-PLANS = tuple((n, 0) for n in LENGTHS) + tuple((n, 1) for n in VARIANT1)
+VARIANT2 = (4096,)
+PLANS = (tuple((n, 0) for n in LENGTHS) + tuple((n, 1) for n in VARIANT1) +
+         tuple((n, 2) for n in VARIANT2))
 ARCH = "gfx950"
 
 

@@ -3,10 +3,11 @@
 // line) and the radix sequence of the Stockham passes (every radix divides
 // E).  Column passes process tiles of C adjacent columns (C lines interleaved
 // in LDS); row passes process LR rows per workgroup.  Variant 0 is the
-// default of every length; variant 1, where it exists, is an alternative
-// schedule (other E, radices, tile width or rows per workgroup) that the
-// batched solver's autotuner may pick after measuring both, and that the
-// single-array passes use where it measured faster.  A split plan (SPLIT)
+// default of every length; variants 1 and 2, where they exist, are
+// alternative schedules (other E, radices, tile width or rows per
+// workgroup) that the batched solver's autotuner may pick after measuring
+// them, and that the single-array passes use where they measured faster.
+// A split plan (SPLIT)
 // exchanges through half the LDS, in two rounds, for rows and columns.
 #pragma once
 
@@ -66,6 +67,8 @@ CSSAR_PLAN(2048, 1, 16, 4, 256, 16, 16, 8)
 CSSAR_PLAN(3072, 0, 24, 4, 512, 3, 8, 8, 8, 2)
 CSSAR_PLAN(4096, 0, CSSAR_E4096, CSSAR_C4096, CSSAR_RT4096, 16, 16, 16)
 CSSAR_PLAN(4096, 1, 32, 4, 256, 16, 16, 16)
+// two-column tiles (half the LDS of a four-column tile: two workgroups per CU)
+CSSAR_PLAN(4096, 2, 16, 2, 512, 16, 16, 16)
 CSSAR_PLAN(8192, 0, 16, 2, 512, 16, 16, 16, 2)
 // 8192-point lines through half the LDS: four-column tiles, and two rows per
 // row-pass workgroup (two workgroups per CU)
@@ -89,8 +92,8 @@ constexpr bool plan_ok() {
 // Every (length, variant) pair that is compiled.
 #define CSSAR_FOR_EACH_PLAN(X)                                                    \
   X(64, 0) X(128, 0) X(256, 0) X(512, 0) X(512, 1) X(768, 0) X(1024, 0) X(1024, 1) \
-  X(1536, 0) X(1536, 1) X(2048, 0) X(2048, 1) X(3072, 0) X(4096, 0) X(4096, 1) X(8192, 0) \
-  X(8192, 1)
+  X(1536, 0) X(1536, 1) X(2048, 0) X(2048, 1) X(3072, 0) X(4096, 0) X(4096, 1) X(4096, 2) \
+  X(8192, 0) X(8192, 1)
 
 #define CSSAR_CHECK_PLAN(NN, VV) static_assert(plan_ok<Plan<NN, VV>>(), "plan");
 CSSAR_FOR_EACH_PLAN(CSSAR_CHECK_PLAN)
@@ -99,6 +102,6 @@ CSSAR_FOR_EACH_PLAN(CSSAR_CHECK_PLAN)
 #define CSSAR_FOR_EACH_LENGTH(X) \
   X(64) X(128) X(256) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096) X(8192)
 
-constexpr int kMaxVariants = 2;
+constexpr int kMaxVariants = 3;
 
 }  // namespace cssar
