@@ -126,12 +126,13 @@ int occupancy(const void* fn, int block) {
 // Plan variant of the single-array column pass of each kind (also the
 // batched solver's default).  At 4096 the residual pass runs variant 1 (32
 // elements per thread, 512 threads, the next tile's input loaded during the
-// transforms): 100 us against 107 with variant 0 on MI355X, where variant 1
-// is slower for the update pass (102 against 95: its hoisted twiddles need
-// 16 elements per thread) and the first forward pass.  At 2048 the update
-// pass runs variant 1 (4-column tiles, two workgroups per compute unit):
-// 23.8 against 26.9 us at 2048 x 2048, the residual pass 38.4 against 37.2.
-// CSSAR_COL_V4096 / CSSAR_COL_V2048 = 0 keep variant 0 for every pass.
+// transforms): 100 us against 107 with variant 0 on MI355X (before its
+// reduction lost its fences: 87 us now), where variant 1 is slower for the
+// update pass (102 against 96) and the first forward pass; the update pass
+// runs variant 2 (two-column tiles, two workgroups per compute unit: 90
+// against 96 us).  At 2048 the update pass runs variant 1 (4-column tiles,
+// two workgroups per compute unit): 23.8 against 26.9 us at 2048 x 2048.
+// CSSAR_COL_V4096 / CSSAR_COL_A4096 / CSSAR_COL_V2048 = 0 keep variant 0.
 #ifndef CSSAR_COL_V4096
 #define CSSAR_COL_V4096 1
 #endif
@@ -156,15 +157,10 @@ int row_variant(int n) { return n == 8192 ? CSSAR_V8192 : 0; }
 int column_variant(int n, int which) {
   // 8192: the first forward and the inverse passes on four-column tiles
   if (n == 8192) return (which == CK_FWD || which == CK_INV) ? CSSAR_V8192 : 0;
+  // (the threshold adjoint recomputes the update pass's V: same plan, same
+  // support decisions)
   if (n == 4096 && which == CK_R) return CSSAR_COL_V4096;
-  // the update pass (and the threshold adjoint, which recomputes its V on the
-  // same plan) on two-column tiles: 90-92 against 96 us
   if (n == 4096 && (which == CK_A || which == CK_VB)) return CSSAR_COL_A4096;
-  // (the threshold adjoint recomputes the update pass's V: same plan, same support)
-#ifndef CSSAR_COL_R2048
-#define CSSAR_COL_R2048 0
-#endif
-  if (n == 2048 && which == CK_R) return CSSAR_COL_R2048;
   if (n == 2048 && (which == CK_A || which == CK_VB)) return CSSAR_COL_V2048;
   return 0;
 }
