@@ -133,12 +133,11 @@ def ita_states(y, mask, lam, iters, geom, mu=1.0):
     """Forward pass keeping every iterate: (X[0..K], V[0..K-1], R[0..K-1]),
     the same iteration as oracle.ita.ita."""
     y = np.asarray(y, dtype=np.complex128)
-    m = np.asarray(mask, dtype=np.float64)
     X = [np.zeros_like(y)]
     V, R = [], []
     for _ in range(int(iters)):
         x = X[-1]
-        r = m * (y - _csa.G(x, geom)) if np.any(x) else m * y
+        r = _ita._sampled(mask, y - _csa.G(x, geom)) if np.any(x) else _ita._sampled(mask, y)
         v = x + mu * _csa.M(r, geom)
         R.append(r)
         V.append(v)

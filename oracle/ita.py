@@ -22,6 +22,14 @@ from . import csa as _csa
 from . import rda as _rda
 
 
+def _sampled(mask, a):
+    """Theta^T Theta a: the entries of a at sampled positions, 0 elsewhere.
+    Entries outside the mask are dropped whatever their value (the sampling
+    operator of eq. (model) selects the measured samples, and its transpose
+    zero-fills), so a non-finite value there does not reach the result."""
+    return np.where(np.asarray(mask, dtype=bool), a, 0.0)
+
+
 def _G(x, geom):
     """G of the focusing chain geom describes (chirp scaling or range-Doppler)."""
     return _rda.G(x, geom) if isinstance(geom, _rda.RdaGeometry) else _csa.G(x, geom)
@@ -51,14 +59,13 @@ def ita(y, mask, lam, iters, geom, mu=1.0, x0=None):
     ``x0`` (default 0) is the starting iterate.
     """
     y = np.asarray(y, dtype=np.complex128)
-    m = np.asarray(mask, dtype=np.float64)
     x = np.zeros_like(y) if x0 is None else np.array(x0, dtype=np.complex128)
     hist = []
     for _ in range(int(iters)):
         if np.any(x):
-            r = m * (y - _G(x, geom))
+            r = _sampled(mask, y - _G(x, geom))
         else:
-            r = m * y  # G is linear, so G(0) = 0
+            r = _sampled(mask, y)  # G is linear, so G(0) = 0
         hist.append(float(np.vdot(r, r).real))
         dx = _M(r, geom)
         x = soft_threshold(x + mu * dx, lam * mu)
@@ -69,7 +76,7 @@ def lambda_from_sparsity(y, mask, k, geom, mu=1.0):
     """Section IV.B: lambda = |b_mu(x)|_{k+1} / mu, the (k+1)-th largest
     magnitude of b_mu(x) = x + mu dx, taken once at x = X^(0) = 0, where
     b_mu(0) = mu M(m o y)."""
-    b = mu * _M(np.asarray(mask, dtype=np.float64) * np.asarray(y), geom)
+    b = mu * _M(_sampled(mask, np.asarray(y, dtype=np.complex128)), geom)
     mags = np.sort(np.abs(b).ravel())[::-1]
     return float(mags[int(k)] / mu)
 
@@ -77,7 +84,7 @@ def lambda_from_sparsity(y, mask, k, geom, mu=1.0):
 def objective(x, y, mask, lam, geom):
     """1/2 ||m o (y - G x)||^2 + lambda ||x||_1, the objective whose
     proximal-gradient step with threshold lambda*mu is eq. (th2d)."""
-    r = np.asarray(mask, dtype=np.float64) * (y - _G(x, geom))
+    r = _sampled(mask, y - _G(x, geom))
     return 0.5 * float(np.vdot(r, r).real) + lam * float(np.abs(x).sum())
 
 
@@ -107,7 +114,7 @@ def normalized_step(dx, support, mask, geom):
     num = float(np.vdot(dxk, dxk).real)
     if num == 0.0:
         return 1.0
-    gk = np.asarray(mask, dtype=np.float64) * _G(dxk, geom)
+    gk = _sampled(mask, _G(dxk, geom))
     den = float(np.vdot(gk, gk).real)
     return num / den if den > 0.0 else 1.0
 
@@ -125,11 +132,10 @@ def ita_adaptive(y, mask, k, iters, geom, x0=None):
     ``x0`` (default 0) is the starting iterate.
     Returns (X^(iters), [||R^(i)||^2], [mu_i], [lambda_i])."""
     y = np.asarray(y, dtype=np.complex128)
-    m = np.asarray(mask, dtype=np.float64)
     x = np.zeros_like(y) if x0 is None else np.array(x0, dtype=np.complex128)
     resid, mus, lams = [], [], []
     for _ in range(int(iters)):
-        r = m * (y - _G(x, geom)) if np.any(x) else m * y
+        r = _sampled(mask, y - _G(x, geom)) if np.any(x) else _sampled(mask, y)
         resid.append(float(np.vdot(r, r).real))
         dx = _M(r, geom)
         mu = normalized_step(dx, x != 0, mask, geom)
@@ -150,7 +156,7 @@ def safeguard_bound(x_new, x, mask, geom, c):
     +inf when the denominator is 0 (no measured change: no bound)."""
     d = np.asarray(x_new, dtype=np.complex128) - np.asarray(x, dtype=np.complex128)
     num = float(np.vdot(d, d).real)
-    gd = np.asarray(mask, dtype=np.float64) * _G(d, geom)
+    gd = _sampled(mask, _G(d, geom))
     den = float(np.vdot(gd, gd).real)
     return (1.0 - c) * num / den if den > 0.0 else np.inf
 
@@ -172,11 +178,10 @@ def ita_adaptive_safeguarded(y, mask, k, iters, geom, c=0.01, kappa=2.0, max_shr
     if not (0.0 < c < 1.0) or not (kappa * (1.0 - c) > 1.0):
         raise ValueError("need 0 < c < 1 and kappa (1 - c) > 1")
     y = np.asarray(y, dtype=np.complex128)
-    m = np.asarray(mask, dtype=np.float64)
     x = np.zeros_like(y) if x0 is None else np.array(x0, dtype=np.complex128)
     resid, mus, lams, shrinks, ratios = [], [], [], [], []
     for _ in range(int(iters)):
-        r = m * (y - _G(x, geom)) if np.any(x) else m * y
+        r = _sampled(mask, y - _G(x, geom)) if np.any(x) else _sampled(mask, y)
         resid.append(float(np.vdot(r, r).real))
         dx = _M(r, geom)
         mu = normalized_step(dx, x != 0, mask, geom)

@@ -136,3 +136,29 @@ def test_residual_history_decreases_for_exact_data():
     g, xt, m, y = _problem((32, 32), 4, 0.6, 6)
     _, hist = ita.ita(y, m, 1e-3, 30, g)
     assert hist[-1] < 1e-2 * hist[0]
+
+
+def test_entries_outside_the_mask_are_ignored():
+    # Theta selects the measured samples (eq. (model)); what y holds at an
+    # unsampled position is not data: a NaN or a large value there changes
+    # nothing, for the fixed and the adaptive iteration and for lambda.
+    shape = (32, 48)
+    g = csa.Geometry(P, shape)
+    y = inputs.random_complex(shape, seed=21)
+    mask = inputs.random_mask(shape, 0.5, seed=22)
+    clean = np.where(mask, y, 0)
+    dirty = clean.copy()
+    off = np.argwhere(~mask)
+    dirty[tuple(off[0])] = np.nan
+    dirty[tuple(off[1])] = 1e30 + 1e30j
+    x1, h1 = ita.ita(clean, mask, 0.05, 4, g)
+    x2, h2 = ita.ita(dirty, mask, 0.05, 4, g)
+    assert np.array_equal(x1, x2) and h1 == h2
+    assert ita.lambda_from_sparsity(dirty, mask, 10, g) == ita.lambda_from_sparsity(clean, mask, 10, g)
+    a1 = ita.ita_adaptive(clean, mask, 10, 3, g)
+    a2 = ita.ita_adaptive(dirty, mask, 10, 3, g)
+    assert np.array_equal(a1[0], a2[0]) and a1[1:] == a2[1:]
+    # a NaN at a sampled position does propagate (it is data)
+    bad = clean.copy()
+    bad[tuple(np.argwhere(mask)[0])] = np.nan
+    assert not np.all(np.isfinite(ita.ita(bad, mask, 0.05, 1, g)[1]))
