@@ -124,44 +124,32 @@ int occupancy(const void* fn, int block) {
 }
 
 // Plan variant of the single-array column pass of each kind (also the
-// batched solver's default).  At 4096 the residual pass runs variant 1 (32
-// elements per thread, 512 threads, the next tile's input loaded during the
-// transforms): 100 us against 107 with variant 0 on MI355X (before its
-// reduction lost its fences: 87 us now), where variant 1 is slower for the
-// update pass (102 against 96) and the first forward pass; the update pass
-// runs variant 2 (two-column tiles, two workgroups per compute unit: 90
-// against 96 us).  At 2048 the update pass runs variant 1 (4-column tiles,
-// two workgroups per compute unit): 23.8 against 26.9 us at 2048 x 2048.
-// CSSAR_COL_V4096 / CSSAR_COL_A4096 / CSSAR_COL_V2048 = 0 keep variant 0.
-#ifndef CSSAR_COL_V4096
-#define CSSAR_COL_V4096 1
-#endif
-#ifndef CSSAR_COL_A4096
-#define CSSAR_COL_A4096 2
-#endif
-#ifndef CSSAR_COL_V2048
-#define CSSAR_COL_V2048 1
-#endif
-// 8192: lines through half the LDS (variant 1) for the row passes of the
-// chirp-scaling chain (two rows per workgroup, two workgroups per CU: 319
-// against 388 us with four rows per workgroup at 8192 x 8192) and the first
-// forward and the inverse column passes (four-column tiles: 738 against 786
-// us); the update and residual passes run variant 0 (two-column tiles, 16
-// elements per thread, 1024 threads: 515 and 478 us against 533 and 503 us
-// with variant 1 for the residual pass and 32 elements per thread for the
-// update pass); 0 keeps variant 0 everywhere.
-#ifndef CSSAR_V8192
-#define CSSAR_V8192 1
-#endif
-int row_variant(int n) { return n == 8192 ? CSSAR_V8192 : 0; }
+// batched solver's default), and of the chirp-scaling row passes, as
+// measured on MI355X:
+// - 4096: the residual pass runs variant 1 (32 elements per thread, 512
+//   threads, the next tile's input loaded during the transforms: 100 us
+//   against 107 with variant 0, measured with the fenced reduction of the
+//   time); variant 1 is slower for the update pass (102 against 96 us) and
+//   the first forward pass.  The update pass runs variant 2 (two-column
+//   tiles, two workgroups per compute unit: 90 against 96 us).
+// - 2048: the update pass runs variant 1 (4-column tiles, two workgroups
+//   per compute unit): 23.8 against 26.9 us at 2048 x 2048.
+// - 8192: lines through half the LDS (variant 1) for the chirp-scaling row
+//   passes (two rows per workgroup, two workgroups per CU: 319 against 388
+//   us with four rows per workgroup at 8192 x 8192) and the first forward
+//   and the inverse column passes (four-column tiles: 738 against 786 us);
+//   the update and residual passes run variant 0 (two-column tiles, 16
+//   elements per thread, 1024 threads: 515 and 478 us against 533 and 503
+//   us with variant 1 for the residual pass and 32 elements per thread for
+//   the update pass).
+// (The threshold adjoint recomputes the update pass's V: same plan, same
+// support decisions.)
+int row_variant(int n) { return n == 8192 ? 1 : 0; }
 int column_variant(int n, int which) {
-  // 8192: the first forward and the inverse passes on four-column tiles
-  if (n == 8192) return (which == CK_FWD || which == CK_INV) ? CSSAR_V8192 : 0;
-  // (the threshold adjoint recomputes the update pass's V: same plan, same
-  // support decisions)
-  if (n == 4096 && which == CK_R) return CSSAR_COL_V4096;
-  if (n == 4096 && (which == CK_A || which == CK_VB)) return CSSAR_COL_A4096;
-  if (n == 2048 && (which == CK_A || which == CK_VB)) return CSSAR_COL_V2048;
+  if (n == 8192) return (which == CK_FWD || which == CK_INV) ? 1 : 0;
+  if (n == 4096 && which == CK_R) return 1;
+  if (n == 4096 && (which == CK_A || which == CK_VB)) return 2;
+  if (n == 2048 && (which == CK_A || which == CK_VB)) return 1;
   return 0;
 }
 
@@ -180,11 +168,6 @@ ColArgs col_args(const cssar_op* op) {
   a.mu = 1.0f;
   a.partials = op->partials;
   a.status = op->counter + 1;
-  a.rowc1 = op->rowc1;
-  a.rowc3 = op->rowc3;
-  a.inv_fs = 1.0 / op->p.fs;
-  a.fc_fs = op->p.fc / op->p.fs;
-  a.p_c = op->p.fc * 2.0 * op->p.r_ref / kC;
   return a;
 }
 
@@ -257,15 +240,6 @@ int residual_total(cssar_op* op, int ck, const ColArgs& a, bool check, hipStream
                      op->grid_col[ck], a.hist_out, a.status);
   HIP_TRY(hipGetLastError());
   return CSSAR_OK;
-}
-
-int launch_row_mid(cssar_op* op, const RowArgs& a, hipStream_t s) {
-  return timed(op, a.conj ? 1 : 0, s, [&] { return op->krow->row_mid(a, op->grid_row, s); });
-}
-
-int launch_col_scr(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
-  const KernelTable* kt = op->kcol[which];
-  return timed(op, 2 + which, s, [&] { return kt->col_scr[which](a, op->grid_col[which], s); });
 }
 
 int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s) {
@@ -470,23 +444,6 @@ int cssar_apply_G(cssar_op* op, const void* x, void* y_out, void* ws, void* stre
   return launch_col(op, CK_INV, a, s);
 }
 
-// The solver's iteration with the range-Doppler screens moved into the
-// column passes (the row passes keep only the 2-D frequency screen).  The
-// state is Xh = Phi3* o F_eta X (Phi3 applied on the update pass's input
-// and its conjugate on its output), so per iteration:
-//   row (Phi2*):      P = F_tau^-1 Phi2* F_tau Xh      = Phi1 o F_eta G X
-//   column residual:  Phi1* P -> residual -> F_eta R  -> Phi1 o F_eta R
-//   row (Phi2):       P = F_tau^-1 Phi2 F_tau P        = Phi3* o F_eta M R
-//   column update:    Phi3 (Xh + mu P) = F_eta X + mu F_eta M R -> threshold
-//                     -> Phi3* F_eta X+ (or X+ in the last iteration).
-// CSSAR_SCREENED 1 runs this screened schedule; 0 (default) keeps all
-// screens in the row passes.  Measured at 4096 on MI355X: screened rows
-// 60.5 us (unscreened 72) but screened update / residual passes 114 / 120 us
-// (97 / 108): the column passes slow down with their added work, so the
-// unscreened schedule is faster overall (345 vs 351 us per iteration).
-#ifndef CSSAR_SCREENED
-#define CSSAR_SCREENED 0
-#endif
 int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters,
                     void* x_out, float* resid_hist, void* ws, void* stream) {
   int rc = check_op(op);
@@ -497,14 +454,11 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
   if (x_out == y || x_out == ws || ws == y) return fail(CSSAR_EINVAL, "x_out, y and ws must not alias");
   hipStream_t s = (hipStream_t)stream;
   const size_t blk = align256(b4_bytes(op->na, op->nr));
-  float2* X = (float2*)ws;                       // Xt = F_eta X (or Xh) (blocked layout)
+  float2* X = (float2*)ws;                       // Xt = F_eta X (blocked layout)
   float2* P = (float2*)((char*)ws + blk);        // pass buffer (in place)
   float2* Y = (float2*)((char*)ws + 2 * blk);    // m o y (blocked layout, unsampled marked)
-  const bool scr = CSSAR_SCREENED != 0 && op->chain == CSSAR_CHAIN_CSA;
-  auto col = [&](int which, const ColArgs& a) {
-    return (scr && which != CK_INV) ? launch_col_scr(op, which, a, s) : launch_col(op, which, a, s);
-  };
-  auto row = [&](const RowArgs& a) { return scr ? launch_row_mid(op, a, s) : launch_row(op, a, s); };
+  auto col = [&](int which, const ColArgs& a) { return launch_col(op, which, a, s); };
+  auto row = [&](const RowArgs& a) { return launch_row(op, a, s); };
   ColArgs a = col_args(op);
   a.y = Y;
   a.mask = (const uint32_t*)mask_bits;

@@ -83,41 +83,69 @@ __device__ __forceinline__ void dft8(float2* a) {
   a[7] = csub(e3, o3);
 }
 
+// Product by a twiddle given in the forward convention (conjugated for the
+// inverse transform).
+template <bool INV> __device__ __forceinline__ float2 tw_mul(float2 x, float2 w) {
+  return INV ? cmulc(x, w) : cmul(x, w);
+}
+
+// s = a + w b and d = a - w b (w conjugated for the inverse): the product
+// enters through FMAs and d = 2 a - s, six instructions instead of the eight
+// of a separate product, sum and difference.
 template <bool INV>
-__device__ __forceinline__ void dft16(float2* a) {
-  // 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.
-  // Y_{n2}[k1] = DFT4_{n1}(a[4 n1 + n2]); Z = Y * w16^(n2 k1); X[k1 + 4 k2] = DFT4_{n2}(Z[n2][k1])
+__device__ __forceinline__ void fma_pair(float2 a, float2 w, float2 b, float2& s, float2& d) {
+  const float wy = INV ? -w.y : w.y;
+  s = make_float2(fmaf(w.x, b.x, fmaf(-wy, b.y, a.x)), fmaf(w.x, b.y, fmaf(wy, b.x, a.y)));
+  d = make_float2(fmaf(2.0f, a.x, -s.x), fmaf(2.0f, a.y, -s.y));
+}
+
+// 4-point DFT of (a0, u1 a1, u2 a2, u3 a3): dft4 with its inputs 1..3
+// multiplied by twiddles (forward convention), the products of inputs 2 and 3
+// taken inside fma_pair.  MI2: u2 = w4 = -i (+i inverse), a free product.
+template <bool INV, bool MI2 = false>
+__device__ __forceinline__ void dft4_tw(float2& a0, float2& a1, float2& a2, float2& a3, float2 u1, float2 u2,
+                                        float2 u3) {
+  float2 t0, t1, t2, d;
+  if constexpr (MI2) {
+    const float2 m2 = mul_mi<INV>(a2);
+    t0 = cadd(a0, m2);
+    t1 = csub(a0, m2);
+  } else {
+    fma_pair<INV>(a0, u2, a2, t0, t1);
+  }
+  fma_pair<INV>(tw_mul<INV>(a1, u1), u3, a3, t2, d);
+  const float2 t3 = mul_mi<INV>(d);
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+// 16-point DFT as 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.
+// Y_{n2}[k1] = DFT4_{n1}(a[4 n1 + n2]); Z = Y w16^(n2 k1); X[k1 + 4 k2] = DFT4_{n2}(Z[n2][k1]).
+// TW: input m is first multiplied by W[m] (forward convention; W[0] only
+// with TW0), the products taken inside the first stage's butterflies.
+template <bool INV, bool TW = false, bool TW0 = false>
+__device__ __forceinline__ void dft16(float2* a, const float2* W = nullptr) {
 #pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(a[n2], a[4 + n2], a[8 + n2], a[12 + n2]);
-  // now a[4 k1 + n2] holds Y_{n2}[k1]
+  for (int n2 = 0; n2 < 4; ++n2) {
+    if constexpr (TW) {
+      if (TW0 || n2 > 0) a[n2] = tw_mul<INV>(a[n2], W[n2]);
+      dft4_tw<INV>(a[n2], a[4 + n2], a[8 + n2], a[12 + n2], W[4 + n2], W[8 + n2], W[12 + n2]);
+    } else {
+      dft4<INV>(a[n2], a[4 + n2], a[8 + n2], a[12 + n2]);
+    }
+  }
+  // a[4 k1 + n2] holds Y_{n2}[k1]; the second stage over n2 for each k1 with
+  // the twiddles w16^(n2 k1), w16^e = exp(-2 pi i e / 16)
   const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
   const float r = 0.70710678118654752440f;
-  // twiddles w16^(n2 k1) for n2, k1 in 1..3: exponents 1,2,3,2,4,6,3,6,9
-  auto tw = [&](float2 x, int e) -> float2 {
-    // w16^e, e in {1,2,3,4,6,9}; forward w = exp(-2 pi i e / 16)
-    float cr, ci;
-    switch (e) {
-      case 1: cr = c1; ci = -s1; break;
-      case 2: cr = r; ci = -r; break;
-      case 3: cr = s1; ci = -c1; break;
-      case 4: cr = 0.f; ci = -1.f; break;
-      case 6: cr = -r; ci = -r; break;
-      default: cr = -c1; ci = s1; break;  // 9: exp(-2 pi i 9/16) = -c1 + i s1
-    }
-    if (INV) ci = -ci;
-    return make_float2(fmaf(x.x, cr, -x.y * ci), fmaf(x.x, ci, x.y * cr));
-  };
-  a[4 * 1 + 1] = tw(a[4 * 1 + 1], 1);
-  a[4 * 1 + 2] = tw(a[4 * 1 + 2], 2);
-  a[4 * 1 + 3] = tw(a[4 * 1 + 3], 3);
-  a[4 * 2 + 1] = tw(a[4 * 2 + 1], 2);
-  a[4 * 2 + 2] = mul_mi<INV>(a[4 * 2 + 2]);
-  a[4 * 2 + 3] = tw(a[4 * 2 + 3], 6);
-  a[4 * 3 + 1] = tw(a[4 * 3 + 1], 3);
-  a[4 * 3 + 2] = tw(a[4 * 3 + 2], 6);
-  a[4 * 3 + 3] = tw(a[4 * 3 + 3], 9);
-#pragma unroll
-  for (int k1 = 0; k1 < 4; ++k1) dft4<INV>(a[4 * k1 + 0], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3]);
+  const float2 e1 = make_float2(c1, -s1), e2 = make_float2(r, -r), e3 = make_float2(s1, -c1);
+  const float2 e6 = make_float2(-r, -r), e9 = make_float2(-c1, s1);
+  dft4<INV>(a[0], a[1], a[2], a[3]);
+  dft4_tw<INV>(a[4], a[5], a[6], a[7], e1, e2, e3);
+  dft4_tw<INV, true>(a[8], a[9], a[10], a[11], e2, e2, e6);
+  dft4_tw<INV>(a[12], a[13], a[14], a[15], e3, e6, e9);
   // a[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 index
   float2 t[16];
 #pragma unroll
@@ -142,38 +170,6 @@ __device__ __forceinline__ void dft_reg(float2* a) {
     static_assert(R == 16, "radix");
     dft16<INV>(a);
   }
-}
-
-// ------------------------------------------------------- sin/cos in turns --
-// sin and cos of 2 pi r for |r| <= 1/8 by their Taylor series (degree 9 and
-// 10; truncation below 2e-9 at |2 pi r| = pi/4), then a quarter-turn
-// rotation by q.  Coefficients are (2 pi)^k / k! with alternating signs.
-__device__ __forceinline__ float2 cis_quadrant(float r, int q) {
-  const float r2 = r * r;
-  const float S1 = 6.28318530717958647693f, S3 = -41.341702240399760234f,
-              S5 = 81.6052492760750542034f, S7 = -76.7058597530613858416f,
-              S9 = 42.058693944897653145f;
-  const float C2 = -19.7392088021787172377f, C4 = 64.939394022668291491f,
-              C6 = -85.456817206693727736f, C8 = 60.2446413718766603627f,
-              C10 = -26.4262567833743974529f;
-  float s = fmaf(r2, S9, S7);
-  s = fmaf(r2, s, S5);
-  s = fmaf(r2, s, S3);
-  s = fmaf(r2, s, S1);
-  s = s * r;
-  float c = fmaf(r2, C10, C8);
-  c = fmaf(r2, c, C6);
-  c = fmaf(r2, c, C4);
-  c = fmaf(r2, c, C2);
-  c = fmaf(r2, c, 1.0f);
-  // rotate by q quarter turns: (c, s) -> (-s, c) per quarter
-  float cc = (q & 1) ? -s : c;
-  float ss = (q & 1) ? c : s;
-  if (q & 2) {
-    cc = -cc;
-    ss = -ss;
-  }
-  return make_float2(cc, ss);
 }
 
 // ------------------------------------------------------------ LDS layout --
@@ -214,6 +210,9 @@ struct TwLds {  // two-level table in LDS: w^e = lo[e % 64] hi[e / 64]
 // persistent kernel computes them once.
 struct TwPowers {
   float2 w[16];
+  // the pass whose twiddles come from an LDS table (table_pass): row j of
+  // the table, tab[j (R + 1) + m] = w^(j m step)
+  const float2* tab;
 };
 
 template <int N, int E, int R, int L, typename TW>
@@ -227,13 +226,16 @@ __device__ __forceinline__ TwPowers tw_powers(int b, const TW& tws) {
     const int hi = 1 << (31 - __builtin_clz(m));
     h.w[m] = (m == hi) ? cmul(h.w[m / 2], h.w[m / 2]) : cmul(h.w[hi], h.w[m - hi]);
   }
+  h.tab = nullptr;
   return h;
 }
 
 // Radix-R butterflies of one Stockham pass on the thread's registers.  The
 // twiddles w^(j m), m < R, come from one lookup of w^j and products of at
-// most four factors for the rest, or from precomputed powers (HP).
-template <int N, int E, int R, int L, bool INV, typename TW, bool HP = false>
+// most four factors for the rest (TM = 0), from precomputed powers (TM = 1),
+// or from the pass's LDS table (TM = 2).  With given twiddles a radix-16
+// butterfly takes their products inside its first stage.
+template <int N, int E, int R, int L, bool INV, typename TW, int TM = 0>
 __device__ __forceinline__ void stockham_compute(float2 (&v)[E], int b, const TW& tws, const TwPowers& hp) {
   constexpr int Q = E / R;
   constexpr int T = N / E;
@@ -242,28 +244,44 @@ __device__ __forceinline__ void stockham_compute(float2 (&v)[E], int b, const TW
     float2 a[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) a[m] = v[q + Q * m];
-    if constexpr (HP) {
+    if constexpr (TM != 0) {
       static_assert(Q == 1 && L > 1, "precomputed twiddles need one butterfly per thread");
+      float2 W[R];
+      if constexpr (TM == 1) {
 #pragma unroll
-      for (int m = 1; m < R; ++m) a[m] = INV ? cmulc(a[m], hp.w[m]) : cmul(a[m], hp.w[m]);
-    } else if constexpr (L > 1) {
-      const int beta = b + T * q;
-      const int j = beta % L;
-      constexpr int step = N / (L * R);
-      // w^m = w^hi * w^(m - hi) with hi the highest power of two <= m; each
-      // product is applied as soon as it exists
-      float2 w[R];
-      w[1] = tws(j * step);
-      if (INV) w[1].y = -w[1].y;
-      a[1] = cmul(a[1], w[1]);
+        for (int m = 1; m < R; ++m) W[m] = hp.w[m];
+      } else {
+        const float2* row = hp.tab + (b % L) * (R + 1);
 #pragma unroll
-      for (int m = 2; m < R; ++m) {
-        const int hi = 1 << (31 - __builtin_clz(m));
-        w[m] = (m == hi) ? cmul(w[m / 2], w[m / 2]) : cmul(w[hi], w[m - hi]);
-        a[m] = cmul(a[m], w[m]);
+        for (int m = 1; m < R; ++m) W[m] = row[m];
       }
+      if constexpr (R == 16) {
+        dft16<INV, true>(a, W);
+      } else {
+#pragma unroll
+        for (int m = 1; m < R; ++m) a[m] = tw_mul<INV>(a[m], W[m]);
+        dft_reg<R, INV>(a);
+      }
+    } else {
+      if constexpr (L > 1) {
+        const int beta = b + T * q;
+        const int j = beta % L;
+        constexpr int step = N / (L * R);
+        // w^m = w^hi * w^(m - hi) with hi the highest power of two <= m; each
+        // product is applied as soon as it exists
+        float2 w[R];
+        w[1] = tws(j * step);
+        if (INV) w[1].y = -w[1].y;
+        a[1] = cmul(a[1], w[1]);
+#pragma unroll
+        for (int m = 2; m < R; ++m) {
+          const int hi = 1 << (31 - __builtin_clz(m));
+          w[m] = (m == hi) ? cmul(w[m / 2], w[m / 2]) : cmul(w[hi], w[m - hi]);
+          a[m] = cmul(a[m], w[m]);
+        }
+      }
+      dft_reg<R, INV>(a);
     }
-    dft_reg<R, INV>(a);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[q + Q * m] = a[m];
     if constexpr (Q > 1) __builtin_amdgcn_sched_barrier(0);
@@ -359,6 +377,57 @@ __device__ __forceinline__ void stockham_exchange_split(float2 (&v)[E], int b, i
   for (int k = 0; k < E; ++k) v[k] = t[k];
 }
 
+// Passes whose twiddles a thread can precompute for every line: a pass
+// s >= 1 in which each thread holds exactly one butterfly (R = E), so that
+// its butterfly index j = b mod L does not change between lines.  The last
+// such pass (the most distinct twiddles) keeps its powers in registers
+// (hoisted_pass); an earlier one with at most 512 table entries reads them
+// from a small LDS table filled once per workgroup (table_pass).  -1: none.
+template <class P>
+constexpr int hoisted_pass() {
+  int h = -1;
+  for (int s = 1; s < P::P; ++s)
+    if (P::radix(s) == P::E && P::radix(s) <= 16) h = s;
+  return h;
+}
+template <class P>
+constexpr int table_pass() {
+  int t = -1;
+  for (int s = 1; s < hoisted_pass<P>(); ++s)
+    if (P::radix(s) == P::E && P::sub(s) * (P::radix(s) + 1) <= 512) t = s;
+  return t;
+}
+// Entries of the table pass's LDS table (one row of R + 1 per butterfly
+// index j, padded against bank conflicts); 1 when there is none.
+template <class P>
+constexpr int pass_table_size() {
+  return table_pass<P>() < 0 ? 1 : P::sub(table_pass<P>()) * (P::radix(table_pass<P>()) + 1);
+}
+
+// Fill the table pass's twiddles tab[j (R + 1) + m] = w_N^(j m step) from the
+// global table (all threads of the workgroup; a barrier must follow).
+template <class P>
+__device__ __forceinline__ void load_pass_table(float2* t, const float2* __restrict__ tw) {
+  constexpr int s = table_pass<P>();
+  if constexpr (s >= 0) {
+    constexpr int R = P::radix(s), L = P::sub(s), step = P::N / (L * R);
+    for (int i = threadIdx.x; i < L * (R + 1); i += blockDim.x) {
+      const int j = i / (R + 1), m = i % (R + 1);
+      t[i] = m < R ? tw[j * m * step] : make_float2(0.f, 0.f);
+    }
+  }
+}
+
+// The hoisted pass's twiddle powers of thread b (computed once per kernel),
+// with the table pass's LDS table.
+template <class P, typename TW>
+__device__ __forceinline__ TwPowers hoist_powers(int b, const TW& tws, const float2* tab) {
+  constexpr int s = hoisted_pass<P>();
+  TwPowers h = tw_powers<P::N, P::E, P::radix(s), P::sub(s)>(b, tws);
+  h.tab = tab;
+  return h;
+}
+
 // One length-N transform (plan P) of the line held by the thread's
 // registers (x[b + T k] in v[k]), lines interleaved C-wide in LDS (of N or,
 // with SPL, N/2 points per line).
@@ -370,7 +439,8 @@ __device__ __forceinline__ void fft_line(float2 (&v)[P::E], int b, int c, float2
     constexpr int R = P::radix(S);
     constexpr int L = P::sub(S);
     __builtin_amdgcn_sched_barrier(0);
-    stockham_compute<N, P::E, R, L, INV, TW, S == HS>(v, b, tws, hp);
+    constexpr int TS = HS >= 0 ? table_pass<P>() : -1;
+    stockham_compute<N, P::E, R, L, INV, TW, S == HS ? 1 : (S == TS ? 2 : 0)>(v, b, tws, hp);
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (S + 1 < P::P) {
       if constexpr (SPL) stockham_exchange_split<N, P::E, R, L, C>(v, b, c, lds);
@@ -385,13 +455,6 @@ template <class P, bool INV, int C, typename TW, bool SPL = false>
 __device__ __forceinline__ void fft_line(float2 (&v)[P::E], int b, int c, float2* lds, const TW& tws) {
   TwPowers none;
   fft_line<P, INV, C, TW, 0, -1, SPL>(v, b, c, lds, tws, none);
-}
-
-// Pass whose twiddles a thread can precompute for every line (-1: none):
-// the second pass, when each thread holds exactly one butterfly of it.
-template <class P>
-constexpr int hoisted_pass() {
-  return (P::P >= 2 && P::radix(1) == P::E && P::radix(1) <= 16) ? 1 : -1;
 }
 
 // Fill a two-level twiddle table (64 + N/64 entries) from the global table.
@@ -423,26 +486,15 @@ __device__ __forceinline__ Quad quad_in_slot(double p0, double p1, double p2, in
   return q;
 }
 
-// 1: the hardware sine/cosine (argument in turns, |error| <= 1.3e-7 on
-// [-1/2, 1/2] measured on gfx950) after the FP64 reduction; 0: the Taylor
-// polynomial of cis_quadrant.
-#ifndef CSSAR_HWSIN
-#define CSSAR_HWSIN 1
-#endif
-
-// exp(2 pi i (A + B k + C k^2)) for a small integer k.
+// exp(2 pi i (A + B k + C k^2)) for a small integer k: the argument in FP64
+// turns, reduced to [-1/2, 1/2] in FP64, then the hardware FP32 sine and
+// cosine of the remainder (argument in turns; |error| <= 1.3e-7 on
+// [-1/2, 1/2], measured on gfx950).
 __device__ __forceinline__ float2 cis_quad(const Quad& q, int k) {
   const double dk = (double)k;
-#if CSSAR_HWSIN
   const double t = fma(fma(q.C, dk, q.B), dk, q.A);
   const float r = (float)(t - rint(t));  // |r| <= 1/2 turn
   return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
-#else
-  const double t4 = 4.0 * fma(fma(q.C, dk, q.B), dk, q.A);  // quarter turns
-  const double qn = rint(t4);
-  const float r = (float)((t4 - qn) * 0.25);
-  return cis_quadrant(r, (int)qn);
-#endif
 }
 
 // exp(2 pi i t) for an FP64 argument in turns: FP64 reduction to

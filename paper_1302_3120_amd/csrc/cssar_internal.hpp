@@ -111,8 +111,6 @@ int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s);
 // (if check or a.hist_out).
 int residual_total(cssar_op* op, int ck, const ColArgs& a, bool check, hipStream_t s);
 int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s);
-int launch_row_mid(cssar_op* op, const RowArgs& a, hipStream_t s);
-int launch_col_scr(cssar_op* op, int which, const ColArgs& a, hipStream_t s);
 
 // Bytes of the support bits of the adaptive solver's column passes.
 size_t support_bytes(const cssar_op* op);

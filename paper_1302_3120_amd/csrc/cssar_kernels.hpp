@@ -152,10 +152,6 @@ struct ColArgs {
   float* hist_out;       // R, masked FWD: where the total ||R||^2 goes (may be NULL; the
                          // passes write per-block partials, a one-block kernel the total)
   unsigned* status;      // bit 0: non-finite norm (set by the one-block total kernels)
-  // screened column passes (range-Doppler screens moved out of the row passes)
-  const double2* rowc1;  // per Doppler bin: Phi1 (a1, d1)
-  const double2* rowc3;  //                  Phi3 (D, b3)
-  double inv_fs, fc_fs, p_c;
   // adaptive passes
   AdaptState* ad;        // step, threshold, ||dX_G||^2
   uint32_t* supp;        // D (read), T (written): support bits, word tile * CT + thread,
@@ -308,9 +304,7 @@ struct RowLds {
 // One unit (LR rows) of the row pass of array a:
 //   M: x Phi1 -> F_tau -> x Phi2 / N_r -> F_tau^-1 -> x Phi3
 //   G: x Phi3* -> F_tau -> x Phi2* / N_r -> F_tau^-1 -> x Phi1*
-// CJ: 0 (M) or 1 (G) fixed at compile time, -1 read from a.conj.  MID:
-// only the 2-D frequency screen (the screened column passes apply the
-// range-Doppler ones).
+// CJ: 0 (M) or 1 (G) fixed at compile time, -1 read from a.conj.
 // Per-line tables of the screens' quadratic factors (apply_quad_tab): for
 // each of the LR lines of a unit and each screen, exp(2 pi i C m^2), m <= E/2.
 template <class P>
@@ -335,9 +329,9 @@ __device__ __forceinline__ void row_qtab_fill(const RowArgs& a, int gi, float2* 
   __syncthreads();
 }
 
-template <class P, int CJ = -1, bool MID = false, bool TAB = false>
+template <class P, int CJ = -1>
 __device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane<P>& ln, float2* lds,
-                                         const float2* twl, const TwPowers& hp, float2* qt = nullptr) {
+                                         const float2* twl, const TwPowers& hp, const float2* qt) {
   constexpr int HS = hoisted_pass<P>();
   constexpr int N = P::N, E = P::E, T = P::T, LR = P::LR;
   constexpr int LI = RowLds<P>::LI, LS = RowLds<P>::LS;
@@ -360,59 +354,45 @@ __device__ __forceinline__ void row_unit(const RowArgs& a, int gi, const RowLane
   int loff = (line / LI) * LS;
   asm volatile("" : "+v"(loff));
   const TwLds tws{twl, twl + 64};
-  // the screens: from per-line tables (TAB) or one FP64 evaluation per element
+  // the screens from the per-line tables of their quadratic factors
   constexpr int NQ = RowQTab<P>::NQ;
   const float2* qline = qt + line * RowQTab<P>::PER;  // [Phi1, Phi2, Phi3] x NQ
-  auto screen = [&](auto freq, const Quad& q, int sc, float scale) {
-    constexpr bool F = decltype(freq)::value;
-    if constexpr (TAB) apply_quad_tab<E, F>(v, q, qline + sc * NQ, conj, scale);
-    else apply_quad<E, F>(v, q, conj, scale);
-  };
-  using tau_t = std::integral_constant<bool, false>;
-  using freq_t = std::integral_constant<bool, true>;
   // first range-Doppler screen: Phi1 (M) or Phi3* (G)
-  if constexpr (!MID) {
-    if (conj) screen(tau_t{}, phi3_quad(c3, a, b, T), 2, 1.0f);
-    else screen(tau_t{}, phi1_quad(c1, a, b, T), 0, 1.0f);
-  }
+  if (conj) apply_quad_tab<E, false>(v, phi3_quad(c3, a, b, T), qline + 2 * NQ, true, 1.0f);
+  else apply_quad_tab<E, false>(v, phi1_quad(c1, a, b, T), qline, false, 1.0f);
   fft_line<P, false, LI, TwLds, 0, HS, P::SPLIT>(v, lb, lc, lds + loff, tws, hp);
-  screen(freq_t{}, phi2_quad(c2, b, T), 1, a.scale);
+  apply_quad_tab<E, true>(v, phi2_quad(c2, b, T), qline + NQ, conj, a.scale);
   asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
   fft_line<P, true, LI, TwLds, 0, HS, P::SPLIT>(v, lb, lc, lds + loff, tws, hp);
   // second range-Doppler screen: Phi3 (M) or Phi1* (G)
-  if constexpr (!MID) {
-    if (conj) screen(tau_t{}, phi1_quad(c1, a, b, T), 0, 1.0f);
-    else screen(tau_t{}, phi3_quad(c3, a, b, T), 2, 1.0f);
-  }
+  if (conj) apply_quad_tab<E, false>(v, phi1_quad(c1, a, b, T), qline, true, 1.0f);
+  else apply_quad_tab<E, false>(v, phi3_quad(c3, a, b, T), qline + 2 * NQ, false, 1.0f);
 #pragma unroll
   for (int k = 0; k < E; ++k) out.st(v[k], vo, T * k * 32);
 }
 
-#ifndef CSSAR_ROW_QTAB
-#define CSSAR_ROW_QTAB 1
-#endif
-
-template <class P, int CJ, bool MID>
+template <class P, int CJ>
 __global__ __launch_bounds__(P::RT, RowLds<P>::waves_per_eu) void row_pass_kernel(RowArgs a) {
   if (a.gate && *a.gate == 0u) return;  // (uniform over the grid)
   __shared__ float2 lds[RowLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
   __shared__ float2 qtab[2 * RowQTab<P>::size];  // double-buffered per unit
+  __shared__ float2 ptab[pass_table_size<P>()];
   load_twiddle_table<P::N>(twl, a.tw);
+  load_pass_table<P>(ptab, a.tw);
   __syncthreads();
   const RowLane<P> ln;
   TwPowers hp;
   if constexpr (hoisted_pass<P>() >= 0)
-    hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(ln.b, TwLds{twl, twl + 64});
+    hp = hoist_powers<P>(ln.b, TwLds{twl, twl + 64}, ptab);
   const int units = a.na / P::LR;  // N_a is a multiple of LR
-  constexpr bool TAB = CSSAR_ROW_QTAB != 0;
   int par = 0;
   for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x) {
     // the barrier of the fill also orders this unit's table against the
     // previous reader of the same buffer (two units ago)
     float2* qt = qtab + par * RowQTab<P>::size;
-    if constexpr (TAB) row_qtab_fill<P>(a, gi, qt);
-    row_unit<P, CJ, MID, TAB>(a, gi, ln, lds, twl, hp, qt);
+    row_qtab_fill<P>(a, gi, qt);
+    row_unit<P, CJ>(a, gi, ln, lds, twl, hp, qt);
     par ^= 1;
   }
 }
@@ -423,19 +403,20 @@ __global__ __launch_bounds__(P::RT) void row_group_kernel(GroupArgs g) {
   __shared__ float2 twl[64 + P::N / 64];
   __shared__ float2 qtab[2 * RowQTab<P>::size];
   const RowArgs* __restrict__ args = (const RowArgs*)g.args;
+  __shared__ float2 ptab[pass_table_size<P>()];
   load_twiddle_table<P::N>(twl, args[0].tw);  // w_N depends on N only
+  load_pass_table<P>(ptab, args[0].tw);
   __syncthreads();
   const RowLane<P> ln;
   TwPowers hp;
   if constexpr (hoisted_pass<P>() >= 0)
-    hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(ln.b, TwLds{twl, twl + 64});
-  constexpr bool TAB = CSSAR_ROW_QTAB != 0;
+    hp = hoist_powers<P>(ln.b, TwLds{twl, twl + 64}, ptab);
   int par = 0;
   for (int u = xcd_logical_block(); u < g.total; u += gridDim.x) {
     const int s = group_find(g.start, g.count, u);
     float2* qt = qtab + par * RowQTab<P>::size;
-    if constexpr (TAB) row_qtab_fill<P>(args[s], u - g.start[s], qt);
-    row_unit<P, CJ, false, TAB>(args[s], u - g.start[s], ln, lds, twl, hp, qt);
+    row_qtab_fill<P>(args[s], u - g.start[s], qt);
+    row_unit<P, CJ>(args[s], u - g.start[s], ln, lds, twl, hp, qt);
     par ^= 1;
   }
 }
@@ -623,12 +604,14 @@ __global__ __launch_bounds__(P::RT) void row_rda_kernel(RowArgs a) {
   if (a.gate && *a.gate == 0u) return;  // (uniform over the grid)
   __shared__ float2 lds[RowLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
+  __shared__ float2 ptab[pass_table_size<P>()];
   load_twiddle_table<P::N>(twl, a.tw);
+  load_pass_table<P>(ptab, a.tw);
   __syncthreads();
   const RowLane<P> ln;
   TwPowers hp;
   if constexpr (hoisted_pass<P>() >= 0)
-    hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(ln.b, TwLds{twl, twl + 64});
+    hp = hoist_powers<P>(ln.b, TwLds{twl, twl + 64}, ptab);
   const int units = a.na / P::LR;
   // (it stages whole lines in LDS: the host uses it with unsplit plans only)
   if constexpr (!P::SPLIT) {
@@ -756,17 +739,17 @@ __global__ __launch_bounds__(P::RT) void row_adj_kernel(RowArgs a) {
 // with 32 elements per thread and at least 4 columns per tile (256 VGPRs
 // per lane at two waves per SIMD); split plans get the overlap from a second
 // workgroup instead.
-#ifndef CSSAR_PIPE_R
-#define CSSAR_PIPE_R 1
-#endif
-#ifndef CSSAR_PIPE_DN
-#define CSSAR_PIPE_DN 1
-#endif
 template <class P, int MODE>
 constexpr bool col_pipelined() {
-  return (MODE == COL_A || (CSSAR_PIPE_R && MODE == COL_R && P::E >= 32 && P::C >= 4) ||
-          (CSSAR_PIPE_DN && (MODE == COL_D || MODE == COL_N))) &&
+  return (MODE == COL_A || (MODE == COL_R && P::E >= 32 && P::C >= 4) || MODE == COL_D || MODE == COL_N) &&
          !P::SPLIT;
+}
+
+// Column passes whose twiddles come precomputed per thread (hoisted_pass,
+// table_pass): the update and residual passes of unsplit plans.
+template <class P, int MODE>
+constexpr bool col_hoisted() {
+  return (MODE == COL_A || MODE == COL_R) && hoisted_pass<P>() >= 0 && !P::SPLIT;
 }
 
 template <class P, int MODE>
@@ -786,31 +769,6 @@ __device__ __forceinline__ void col_preload(const ColArgs& a, int tile, int b, i
   }
 }
 
-// A range-Doppler screen on a column: element (Doppler bin i = b + T k,
-// range column j), from bin i's FP64 coefficients and the column offset
-// o = j - N_r/2 (tau' = o / fs), in turns:
-//   Phi1 = a1 (tau' - d1)^2,  Phi3 = D (p_c + o fc/fs) + b3 tau'^2.
-template <class P, int WHICH, bool CONJ>
-__device__ __forceinline__ void col_screen(float2 (&v)[P::E], const ColArgs& a, int b, int j) {
-  constexpr int E = P::E, T = P::T;
-  const double o = (double)(j - a.nr / 2);
-  const double tau = o * a.inv_fs;
-  const double pj = fma(o, a.fc_fs, a.p_c), tq = tau * tau;
-  const double2* __restrict__ rc = WHICH == 1 ? a.rowc1 : a.rowc3;
-  chunked<E, 4>([&](int k) {
-    const double2 cc = rc[b + T * k];
-    double t;
-    if constexpr (WHICH == 1) {
-      const double u = tau - cc.y;
-      t = cc.x * u * u;
-    } else {
-      t = fma(cc.x, pj, cc.y * tq);
-    }
-    const float2 p = cis_turns(t);
-    v[k] = CONJ ? cmulc(v[k], p) : cmul(v[k], p);
-  });
-}
-
 // Packed sampling mask: bit e % 32 of word e / 32, e = blocked element index
 // of (i, j).  Byte offset and bit of element (b, j), and the byte step per k
 // (element b + T k; T N_r is a multiple of 32).
@@ -822,12 +780,9 @@ __device__ __forceinline__ MaskAddr mask_addr(int b, int j, int T, int nr) {
   return {(e0 >> 5) * 4u, e0 & 31u, (uint32_t)T * (uint32_t)nr / 32u * 4u};
 }
 
-// SCR (screened passes of the solver): the residual pass applies Phi1* on
-// input and Phi1 on output, the update pass Phi3 on input and Phi3* on its
-// azimuth-spectrum output, the first forward pass Phi1 on output; the row
-// passes between them then carry only the 2-D frequency screen Phi2.
-// HT: the second pass's twiddles come precomputed (hp), per thread.
-template <class P, int MODE, bool PIPE = false, bool SCR = false, bool HT = false>
+// HT: the twiddles of the passes a thread can precompute come from hp
+// (hoisted_pass, table_pass).
+template <class P, int MODE, bool PIPE = false, bool HT = false>
 __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int c, float2* lds,
                                           const float2* twl, float2 (&pre)[P::E], int next,
                                           const TwPowers& hp, unsigned* hist0 = nullptr,
@@ -900,7 +855,7 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
     }
     // (split plans and screened passes load m o y after the inverse
     // transform: registers)
-    if constexpr ((MODE == COL_R && !P::SPLIT && !SCR && !HT) || MODE == COL_U) {
+    if constexpr ((MODE == COL_R && !P::SPLIT && !HT) || MODE == COL_U) {
 #pragma unroll
       for (int k = 0; k < E; ++k) y2[k] = yb.f2(ab.voff, k * ab.kstep);
     }
@@ -909,8 +864,6 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
       for (int k = 0; k < E; ++k) y3[k] = in1.f2(ab.voff, k * ab.kstep);
     }
   }
-  if constexpr (SCR && MODE == COL_R) col_screen<P, 1, true>(v, a, b, j);
-  if constexpr (SCR && MODE == COL_A) col_screen<P, 3, false>(v, a, b, j);
   const TwLds tws{twl, twl + 64};
   int lb = b, lc = c;
   asm volatile("" : "+v"(lb), "+v"(lc));  // recompute LDS addresses per tile
@@ -1056,7 +1009,7 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
   } else {  // COL_R: GX = F^-1[W] / N_a; R = m o y - m o GX; out = F R
     fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
     // split plans, screened passes: m o y in chunks of 8 after the transform
-    constexpr bool late = P::SPLIT || SCR || HT;
+    constexpr bool late = P::SPLIT || HT;
     constexpr int YC = late ? 8 : E;
 #pragma unroll
     for (int k0 = 0; k0 < E; k0 += YC) {
@@ -1080,10 +1033,6 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
     asm volatile("" : "+v"(lb), "+v"(lc));
     fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
   }
-  if constexpr (SCR && (MODE == COL_FWD || MODE == COL_R)) col_screen<P, 1, false>(v, a, b, j);
-  if constexpr (SCR && MODE == COL_A) {
-    if (!(a.flags & 2)) col_screen<P, 3, true>(v, a, b, j);
-  }
   if constexpr (MODE != COL_N) {
     const Addr ao = out_layout == RM ? col_addr(RM, b, j, T, a.nr) : ab;
 #pragma unroll
@@ -1102,27 +1051,27 @@ struct ColLds {
   static constexpr int waves_per_eu = P::SPLIT ? wgs * P::CT / 256 : 1;
 };
 
-template <class P, int MODE, bool SCR>
+template <class P, int MODE>
 __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kernel(ColArgs a) {
   constexpr int C = P::C, CT = P::CT;
   if (a.gate && *a.gate == 0u) return;  // (uniform over the grid)
   __shared__ float2 lds[ColLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
   __shared__ float red[CT / 64];
+  __shared__ float2 ptab[pass_table_size<P>()];
   load_twiddle_table<P::N>(twl, a.tw);
+  load_pass_table<P>(ptab, a.tw);
   __syncthreads();
   const int c = threadIdx.x % C;
   const int b = threadIdx.x / C;
   const int ntiles = a.nr / C;  // N_r is a multiple of C
-  // the update and residual passes take the second pass's twiddles from
-  // registers (computed once here) instead of the prefetch
-#ifndef CSSAR_R_HT
-#define CSSAR_R_HT 1
-#endif
-  constexpr bool HT = (MODE == COL_A || (MODE == COL_R && CSSAR_R_HT)) && hoisted_pass<P>() >= 0 && !P::SPLIT;
-  constexpr bool PIPE = col_pipelined<P, MODE>() && !SCR && !HT;
+  // the update and residual passes take the twiddles a thread can
+  // precompute from registers and a small LDS table (set up once here)
+  // instead of the prefetch
+  constexpr bool HT = col_hoisted<P, MODE>();
+  constexpr bool PIPE = col_pipelined<P, MODE>() && !HT;
   TwPowers hp;
-  if constexpr (HT) hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(b, TwLds{twl, twl + 64});
+  if constexpr (HT) hp = hoist_powers<P>(b, TwLds{twl, twl + 64}, ptab);
   float acc = 0.f;
   unsigned chg = 0u;
   float2 pre[P::E];
@@ -1138,7 +1087,7 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   }
   for (; tile < ntiles; tile += gridDim.x) {
     const int next = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : -1;
-    acc += col_unit<P, MODE, PIPE, SCR, HT>(a, tile, b, c, lds, twl, pre, next, hp, hist0, &chg);
+    acc += col_unit<P, MODE, PIPE, HT>(a, tile, b, c, lds, twl, pre, next, hp, hist0, &chg);
   }
   if constexpr (MODE == COL_V) {
     __syncthreads();
@@ -1194,45 +1143,36 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_group_kern
   __shared__ float2 lds[ColLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
   const ColArgs* __restrict__ args = (const ColArgs*)g.args;
+  __shared__ float2 ptab[pass_table_size<P>()];
   load_twiddle_table<P::N>(twl, args[0].tw);
+  load_pass_table<P>(ptab, args[0].tw);
   __syncthreads();
   const int c = threadIdx.x % C;
   const int b = threadIdx.x / C;
   float2 pre[P::E];
   // same per-line arithmetic as the single-array kernel (bit-identical results)
-#ifndef CSSAR_R_HT
-#define CSSAR_R_HT 1
-#endif
-  constexpr bool HT = (MODE == COL_A || (MODE == COL_R && CSSAR_R_HT)) && hoisted_pass<P>() >= 0 && !P::SPLIT;
+  constexpr bool HT = col_hoisted<P, MODE>();
   TwPowers hp;
-  if constexpr (HT) hp = tw_powers<P::N, P::E, P::radix(1), P::sub(1)>(b, TwLds{twl, twl + 64});
+  if constexpr (HT) hp = hoist_powers<P>(b, TwLds{twl, twl + 64}, ptab);
   for (int u = xcd_logical_block(); u < g.total; u += gridDim.x) {
     const int s = group_find(g.start, g.count, u);
-    (void)col_unit<P, MODE, false, false, HT>(args[s], u - g.start[s], b, c, lds, twl, pre, -1, hp);
+    (void)col_unit<P, MODE, false, HT>(args[s], u - g.start[s], b, c, lds, twl, pre, -1, hp);
   }
 }
 
 // Host-side launch helpers (one set per plan, instantiated in kern_inst.hip).
 template <class P>
 struct Kernels {
-  template <bool MID>
-  static hipError_t row_t(const RowArgs& a, int grid, hipStream_t s) {
+  static hipError_t row(const RowArgs& a, int grid, hipStream_t s) {
     if (a.conj)
-      hipLaunchKernelGGL((row_pass_kernel<P, 1, MID>), dim3(grid), dim3(P::RT), 0, s, a);
+      hipLaunchKernelGGL((row_pass_kernel<P, 1>), dim3(grid), dim3(P::RT), 0, s, a);
     else
-      hipLaunchKernelGGL((row_pass_kernel<P, 0, MID>), dim3(grid), dim3(P::RT), 0, s, a);
+      hipLaunchKernelGGL((row_pass_kernel<P, 0>), dim3(grid), dim3(P::RT), 0, s, a);
     return hipGetLastError();
   }
-  static hipError_t row(const RowArgs& a, int grid, hipStream_t s) { return row_t<false>(a, grid, s); }
-  static hipError_t row_mid(const RowArgs& a, int grid, hipStream_t s) { return row_t<true>(a, grid, s); }
   template <int MODE>
   static hipError_t col(const ColArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((col_pass_kernel<P, MODE, false>), dim3(grid), dim3(P::CT), 0, s, a);
-    return hipGetLastError();
-  }
-  template <int MODE>
-  static hipError_t col_scr(const ColArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((col_pass_kernel<P, MODE, true>), dim3(grid), dim3(P::CT), 0, s, a);
+    hipLaunchKernelGGL((col_pass_kernel<P, MODE>), dim3(grid), dim3(P::CT), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t row_group(const GroupArgs& g, int grid, hipStream_t s) {

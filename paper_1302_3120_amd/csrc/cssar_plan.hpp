@@ -40,17 +40,6 @@ template <int N, int V> struct Plan;
   };
 #define CSSAR_PLAN(NN, VV, EE, CC, RTT, ...) CSSAR_PLAN_S(NN, VV, EE, CC, RTT, false, __VA_ARGS__)
 
-#ifndef CSSAR_E4096
-#define CSSAR_E4096 16
-#endif
-#ifndef CSSAR_LR4096
-#define CSSAR_LR4096 2
-#endif
-#ifndef CSSAR_C4096
-#define CSSAR_C4096 4
-#endif
-#define CSSAR_RT4096 (CSSAR_LR4096 * 4096 / CSSAR_E4096)
-
 //         N    V   E   C    RT   radices
 CSSAR_PLAN(64, 0, 16, 16, 256, 16, 4)
 CSSAR_PLAN(128, 0, 16, 16, 256, 16, 8)
@@ -65,7 +54,7 @@ CSSAR_PLAN(1536, 1, 24, 8, 256, 3, 8, 8, 8)
 CSSAR_PLAN(2048, 0, 16, 8, 256, 16, 16, 8)
 CSSAR_PLAN(2048, 1, 16, 4, 256, 16, 16, 8)
 CSSAR_PLAN(3072, 0, 24, 4, 512, 3, 8, 8, 8, 2)
-CSSAR_PLAN(4096, 0, CSSAR_E4096, CSSAR_C4096, CSSAR_RT4096, 16, 16, 16)
+CSSAR_PLAN(4096, 0, 16, 4, 512, 16, 16, 16)
 CSSAR_PLAN(4096, 1, 32, 4, 256, 16, 16, 16)
 // two-column tiles (half the LDS of a four-column tile: two workgroups per CU)
 CSSAR_PLAN(4096, 2, 16, 2, 512, 16, 16, 16)

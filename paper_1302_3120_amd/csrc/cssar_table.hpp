@@ -25,16 +25,12 @@ struct KernelTable {
   hipError_t (*row_group)(const GroupArgs&, int, hipStream_t);
   hipError_t (*col_group[CK_GROUPED])(const GroupArgs&, int, hipStream_t);
   hipError_t (*row_adj[2])(const RowArgs&, int, hipStream_t);  // forward chain M (0) or G (1)
-  hipError_t (*row_mid)(const RowArgs&, int, hipStream_t);     // 2-D frequency screen only
-  hipError_t (*col_scr[CK_GROUPED])(const ColArgs&, int, hipStream_t);  // screened FWD, -, A, R
   hipError_t (*row_rda[2])(const RowArgs&, int, hipStream_t);  // range-Doppler chain M (0), G (1)
   const void* row_fn;
   const void* col_fn[CK_COUNT];
   const void* row_group_fn;
   const void* col_group_fn[CK_GROUPED];
   const void* row_adj_fn[2];
-  const void* row_mid_fn;
-  const void* col_scr_fn[CK_GROUPED];
   const void* row_rda_fn[2];
 };
 

@@ -29,22 +29,19 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
       {&K::template col_group<COL_FWD>, &K::template col_group<COL_INV>,
        &K::template col_group<COL_A>, &K::template col_group<COL_R>},
       {&K::template row_adj<0>, &K::template row_adj<1>},
-      &K::row_mid,
-      {&K::template col_scr<COL_FWD>, &K::template col<COL_INV>, &K::template col_scr<COL_A>,
-       &K::template col_scr<COL_R>},
       {&K::template row_rda<0>, &K::template row_rda<1>},
-      reinterpret_cast<const void*>(&row_pass_kernel<P, 0, false>),
-      {reinterpret_cast<const void*>(&col_pass_kernel<P, COL_FWD, false>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_INV, false>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_A, false>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_R, false>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_VB, false>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_U, false>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_XB, false>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_D, false>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_N, false>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_V, false>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_T, false>)},
+      reinterpret_cast<const void*>(&row_pass_kernel<P, 0>),
+      {reinterpret_cast<const void*>(&col_pass_kernel<P, COL_FWD>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_INV>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_A>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_R>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_VB>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_U>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_XB>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_D>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_N>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_V>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_T>)},
       reinterpret_cast<const void*>(&row_group_kernel<P, 0>),
       {reinterpret_cast<const void*>(&col_group_kernel<P, COL_FWD>),
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_INV>),
@@ -52,11 +49,6 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_R>)},
       {reinterpret_cast<const void*>(&row_adj_kernel<P, 0>),
        reinterpret_cast<const void*>(&row_adj_kernel<P, 1>)},
-      reinterpret_cast<const void*>(&row_pass_kernel<P, 0, true>),
-      {reinterpret_cast<const void*>(&col_pass_kernel<P, COL_FWD, true>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_INV, false>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_A, true>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_R, true>)},
       {reinterpret_cast<const void*>(&row_rda_kernel<P, 0, 8>),
        reinterpret_cast<const void*>(&row_rda_kernel<P, 1, 8>)},
   };
