@@ -34,19 +34,34 @@ PASS_BYTES = {
 # Per pixel per ITA iteration (row G, col R, row M, col A: 80 B) plus the
 # mask (1/8 B): the conventional figure for the fraction of HBM peak.
 ITER_BYTES = 80.125
+# Elements per thread of the sparse-iterate update plans (4096: variant 2,
+# 2048: variant 1, 8192 and the rest: variant 0): one 4-byte support word per
+# E elements.
+UPDATE_E = 16
+
+
+def sparse_update_bytes(nnz_frac):
+    """Algorithmic bytes per pixel of the sparse-iterate update pass: Z read
+    and F_eta X+ written (16), the support words read and written (2 x 4/E),
+    and the nonzeros read and written (2 x 8 x the nonzero fraction)."""
+    return 16.0 + 8.0 / UPDATE_E + 16.0 * nnz_frac
 # Kernel symbol of each pass kind; {v} is the plan variant (the residual
 # column pass at 4096 runs variant 1, see column_variant in cssar_api.hip).
 KIND_SYMBOL = {
-    "row_M": "row_pass_kernel<cssar::Plan<{n}, 0>, 0, false>",
-    "row_G": "row_pass_kernel<cssar::Plan<{n}, 0>, 1, false>",
-    "col_fwd": "col_pass_kernel<cssar::Plan<{n}, 0>, 0, false>",
-    "col_inv": "col_pass_kernel<cssar::Plan<{n}, 0>, 1, false>",
-    "col_update_threshold": "col_pass_kernel<cssar::Plan<{n}, {v}>, 2, false>",
-    "col_residual": "col_pass_kernel<cssar::Plan<{n}, {v}>, 3, false>",
+    "row_M": "row_pass_kernel<cssar::Plan<{n}, {v}>, 0>",
+    "row_G": "row_pass_kernel<cssar::Plan<{n}, {v}>, 1>",
+    "col_fwd": "col_pass_kernel<cssar::Plan<{n}, {v}>, 0>",
+    "col_inv": "col_pass_kernel<cssar::Plan<{n}, {v}>, 1>",
+    "col_update_threshold": "col_pass_kernel<cssar::Plan<{n}, {v}>, 2>",
+    "col_residual": "col_pass_kernel<cssar::Plan<{n}, {v}>, 3>",
+    "col_update_sparse": "col_pass_kernel<cssar::Plan<{n}, {v}>, 11>",
 }
 # plan variant of a pass kind at a line length, where it is not 0 (the
-# library's column_variant for the 4096-point passes)
-KIND_VARIANT = {("col_residual", 4096): 1, ("col_update_threshold", 4096): 2}
+# library's column_variant and row_variant)
+KIND_VARIANT = {("col_residual", 4096): 1, ("col_update_threshold", 4096): 2,
+                ("col_update_sparse", 4096): 2, ("col_update_threshold", 2048): 1,
+                ("col_update_sparse", 2048): 1, ("row_M", 8192): 1, ("row_G", 8192): 1,
+                ("col_fwd", 8192): 1, ("col_inv", 8192): 1}
 
 
 def kind_symbol(kind, n):
@@ -363,7 +378,42 @@ def _rows(pattern):
     return out
 
 
-def rocprof_summary(stats_dir, fetch_dir, write_dir, n, command, title="ITA passes"):
+def sq_summary(sq_dirs, n, kinds):
+    """Per-kernel medians of the SQ counters of one or more rocprofv3 --pmc
+    runs, and what follows from them: VALU instructions per element
+    (SQ_INSTS_VALU counts wave instructions: x 64 lanes / n elements), the
+    time the SIMDs need to issue them (4 cycles per wave instruction on a
+    16-lane SIMD, 1024 SIMDs at 2.4 GHz) and the share of wave time spent
+    waiting (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES)."""
+    vals = {}
+    for d in sq_dirs:
+        for r in _rows(os.path.join(d, "**", "*counter_collection.csv")):
+            if not r["Counter_Name"].startswith("SQ_"):
+                continue
+            vals.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+    lines = ["", "## SQ counters per dispatch (--pmc SQ_*; medians)", ""]
+    names = sorted({c for k in vals.values() for c in k})
+    lines += ["| kernel | " + " | ".join(names) + " | VALU instr / element | VALU issue us "
+              "at 2.4 GHz | wait share |", "|---" * (len(names) + 4) + "|"]
+    for kind in kinds:
+        sym = kind_symbol(kind, n)
+        ks = [k for k in vals if sym in k]
+        if not ks:
+            continue
+        c = {name: statistics.median(v) for name, v in vals[ks[0]].items()}
+        valu = c.get("SQ_INSTS_VALU")
+        per_el = "%.1f" % (valu * 64.0 / (n * n)) if valu else "-"
+        issue = "%.1f" % (valu * 4.0 / (1024 * 2.4e9) * 1e6) if valu else "-"
+        wait = ("%.2f" % (c["SQ_WAIT_INST_ANY"] / c["SQ_WAVE_CYCLES"])
+                if c.get("SQ_WAIT_INST_ANY") and c.get("SQ_WAVE_CYCLES") else "-")
+        lines.append("| %s (%s) | " % (kind, sym) + " | ".join("%.4g" % c.get(nm, float("nan"))
+                                                          for nm in names) +
+                     " | %s | %s | %s |" % (per_el, issue, wait))
+    return lines
+
+
+def rocprof_summary(stats_dir, fetch_dir, write_dir, n, command, title="ITA passes", sq_dirs=()):
     """Text summary of rocprofv3 output: per-kernel durations (kernel-trace
     --stats) and per-dispatch HBM bytes (FETCH_SIZE and WRITE_SIZE runs, each
     scaled so that the calibration copy reads and writes CAL_MIB MiB).  With
@@ -426,13 +476,15 @@ def rocprof_summary(stats_dir, fetch_dir, write_dir, n, command, title="ITA pass
             lines.append("| %s | %d | %.1f | %.1f | %.1f | %.1f |" % (
                 fk[0], cnt, f_kib, w_kib, fb / 1e6, wb / 1e6))
         machine.append("traffic %s %.0f %.0f" % (kind, fb, wb))
-    lines += ["", "Algorithmic bytes per dispatch: 16 B/pixel (row passes), 24 B/pixel (update and "
-                  "residual column passes), 24.125 B/pixel (first column pass: y, mask, two "
-                  "outputs).", "",
+    lines += ["", "Algorithmic bytes per dispatch: 16 B/pixel (row passes), 24 B/pixel (residual "
+                  "column pass), 16 + 8/E + 16 x (nonzero fraction) B/pixel (update pass of the "
+                  "sparse iterate), 24.125 B/pixel (first column pass: y, mask, two outputs).", "",
               "Machine-readable lines (kind, fetch bytes, write bytes per dispatch, scaled):", ""]
     lines += ["    " + m for m in machine]
     lines += ["    kernel_sources_sha256 " + kernel_source_digest(), ""]
-    return "\n".join(lines)
+    if sq_dirs:
+        lines += sq_summary(sq_dirs, n, list(KIND_SYMBOL))
+    return "\n".join(lines) + "\n"
 
 
 def load_traffic():
@@ -482,10 +534,13 @@ def main():
                     help="command line recorded in the --rocprof-summary text")
     ap.add_argument("--summary-title", default="ITA passes",
                     help="title of the --rocprof-summary text")
+    ap.add_argument("--sq-dir", action="append", default=[],
+                    help="rocprofv3 --pmc SQ_* output directories for the --rocprof-summary text")
     args = ap.parse_args()
 
     if args.rocprof_summary:
-        print(rocprof_summary(*args.rocprof_summary, args.size, args.command, args.summary_title))
+        print(rocprof_summary(*args.rocprof_summary, args.size, args.command, args.summary_title,
+                              args.sq_dir))
         return
 
     if args.gpus != 1:
@@ -519,6 +574,14 @@ def main():
     op.sync_status()
     its = args.steps * args.iters / dt
     n = shape[0] * shape[1]
+    # the median of five further timed repeats (the survey's protocol), beside
+    # the contract's single region of exactly --steps steps
+    reps = [args.iters * max(1, args.steps // 2) / time_steps(step, max(1, args.steps // 2), 0)
+            for _ in range(5)]
+    nnz_frac = float(torch.count_nonzero(out)) / n
+    PASS_BYTES["col_update_sparse"] = sparse_update_bytes(nnz_frac)
+    moved = PASS_BYTES["row_G"] + PASS_BYTES["col_residual"] + PASS_BYTES["row_M"] + \
+        PASS_BYTES["col_update_sparse"]
     rec = {
         "metric": METRIC, "value": its, "unit": "iterations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -530,6 +593,13 @@ def main():
                    "shape": list(shape), "iters_per_step": args.iters, "lambda": lam,
                    "nonzeros": k},
         "hbm_frac_algorithmic": ITER_BYTES * n * its / (HBM_PEAK_GBS * 1e9),
+        "repeats_median_iterations_per_s": statistics.median(reps),
+        "repeats_iterations_per_s": reps,
+        # the sparse iterate moves fewer bytes than the 80.125 B/pixel of the
+        # conventional figure: the iteration's own algorithmic bytes
+        "iterate_nonzero_fraction": nnz_frac,
+        "iteration_bytes_per_pixel": moved,
+        "hbm_frac_iteration_bytes": moved * n * its / (HBM_PEAK_GBS * 1e9),
     }
 
     if not args.no_profile:

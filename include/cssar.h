@@ -78,6 +78,18 @@ typedef struct cssar_params {
 
 typedef struct cssar_op cssar_op;
 
+/* Azimuth FM rate at the reference range, K_a = 2 v^2 / (lambda_w r_ref)
+ * with lambda_w = c / fc (the rate of the azimuth matched filter of eq.
+ * (amf)); 0 for NULL or non-positive fc, r_ref.  Host call. */
+double cssar_azimuth_fm_rate(const cssar_params* p);
+
+/* *out = *in with the azimuth FM rate set to Ka (through the velocity,
+ * v = sqrt(Ka lambda_w r_ref / 2)) and the range chirp rate set to Kr: the
+ * parameterisation (K_a, K_r) in which cssar_ita_backward reports its
+ * parameter gradients.  CSSAR_EINVAL for NULL pointers or non-positive or
+ * non-finite rates.  Host call. */
+int cssar_params_with_rates(const cssar_params* in, double Ka, double Kr, cssar_params* out);
+
 /* Build an operator for an n_az x n_rg grid: FP64 per-Doppler-bin and
  * per-range-column coefficient vectors, FP32 twiddle tables, kernel plan.
  * Host call; allocates the operator's small device tables on the current
@@ -113,7 +125,10 @@ int cssar_destroy_operator(cssar_op* op);
 /* Workspace bytes the caller must provide (device memory, 256-byte aligned
  * start; contents need not be initialised and are clobbered):
  *   mode 0: cssar_apply_G / cssar_apply_GH   (one array in the blocked layout)
- *   mode 1: cssar_ita_solve                  (three arrays in the blocked layout)
+ *   mode 1: cssar_ita_solve                  (three arrays in the blocked layout, and
+ *           the sparse iterate: 4 N_a N_r / E bytes of support words, E the
+ *           update plan's elements per thread, a count per column tile and
+ *           2 N_a N_r bytes of value slots)
  *   mode 2: cssar_ita_solve_adaptive         (four arrays in the blocked layout, the
  *           support bits (4 N_a N_r / E bytes, E the column plan's elements per
  *           thread) and 8.5 KB of selection state)
@@ -144,7 +159,11 @@ int cssar_pack_mask(const cssar_op* op, const void* mask_bytes, void* mask_bits,
  * mask_bits: packed mask (cssar_pack_mask); lambda >= 0; iters >= 1;
  * x_out: N_a x N_r complex64 result X^(iters);
  * resid_hist: NULL or a device array of iters floats receiving ||R^(t)||^2;
- * ws: cssar_workspace_size(op, 1) bytes.  No two of y, x_out, ws may alias. */
+ * ws: cssar_workspace_size(op, 1) bytes.  No two of y, x_out, ws may alias.
+ * The iterate is kept spatially, per column tile as its support and nonzero
+ * values (densely where more than a quarter of a tile is nonzero), so a
+ * sparse iterate costs the update pass a read and a write of one array
+ * instead of two reads and a write. */
 int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda,
                     int iters, void* x_out, float* resid_hist, void* ws, void* stream);
 
@@ -303,9 +322,10 @@ const char* cssar_last_error(void);
  * restricted step (adaptive solver), 10 column masked norm and step, 11
  * column pre-threshold value, 12 column threshold at the selected value,
  * 13 adjoint row pass with M forward, 14 adjoint row pass with G forward,
- * 15 selection of the (k+1)-th largest magnitude (all its launches).
+ * 15 selection of the (k+1)-th largest magnitude (all its launches), 16
+ * column update + soft-threshold pass of the sparse iterate (cssar_ita_solve).
  * ms_sum and counts hold CSSAR_PROFILE_KINDS entries. */
-#define CSSAR_PROFILE_KINDS 16
+#define CSSAR_PROFILE_KINDS 17
 int cssar_profile_enable(cssar_op* op, int on);
 int cssar_profile_read(cssar_op* op, double* ms_sum, long* counts);
 

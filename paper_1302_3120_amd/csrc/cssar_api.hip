@@ -148,8 +148,8 @@ int row_variant(int n) { return n == 8192 ? 1 : 0; }
 int column_variant(int n, int which) {
   if (n == 8192) return (which == CK_FWD || which == CK_INV) ? 1 : 0;
   if (n == 4096 && which == CK_R) return 1;
-  if (n == 4096 && (which == CK_A || which == CK_VB)) return 2;
-  if (n == 2048 && (which == CK_A || which == CK_VB)) return 1;
+  if (n == 4096 && (which == CK_A || which == CK_AS || which == CK_VB)) return 2;
+  if (n == 2048 && (which == CK_A || which == CK_AS || which == CK_VB)) return 1;
   return 0;
 }
 
@@ -209,7 +209,41 @@ int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s) {
 }
 
 int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
-  return timed(op, 2 + which, s, [&] { return op->kcol[which]->col[which](a, op->grid_col[which], s); });
+  const int kind = which == CK_AS ? 16 : 2 + which;
+  return timed(op, kind, s, [&] { return op->kcol[which]->col[which](a, op->grid_col[which], s); });
+}
+
+SparseLayout sparse_layout(const cssar_op* op, const KernelTable* kt) {
+  if (!kt) kt = op->kcol[CK_AS];
+  SparseLayout L;
+  L.ntiles = op->nr / kt->C;
+  L.cap = kt->CT * kt->E / 4;  // a quarter of the tile
+  size_t o = align256((size_t)L.ntiles * kt->CT * 4);
+  L.count = o;
+  o += align256((size_t)L.ntiles * 4);
+  L.pool = o;
+  o += align256((size_t)L.ntiles * L.cap * 8);
+  L.bytes = o;
+  return L;
+}
+
+size_t sparse_bytes_max(const cssar_op* op) {
+  size_t m = 0;
+  for (int v = 0; v < kMaxVariants; ++v) {
+    const KernelTable* kt = table_for(op->na, v);
+    if (kt && op->nr % kt->C == 0) m = std::max(m, sparse_layout(op, kt).bytes);
+  }
+  return m;
+}
+
+void set_sparse(const cssar_op* op, ColArgs& a, void* dense, void* base, const KernelTable* kt) {
+  const SparseLayout L = sparse_layout(op, kt);
+  char* b = (char*)base;
+  a.xsupp = (uint32_t*)b;
+  a.xcount = (uint32_t*)(b + L.count);
+  a.xpool = (float2*)(b + L.pool);
+  a.xdense = (float2*)dense;
+  a.xcap = L.cap;
 }
 
 // ||R||^2 of the residual pass (or ||m o y||^2 of the first forward pass)
@@ -250,6 +284,23 @@ int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s) {
 }  // namespace cssar
 
 extern "C" {
+
+double cssar_azimuth_fm_rate(const cssar_params* p) {
+  if (!p || !(p->fc > 0.0) || !(p->r_ref > 0.0)) return 0.0;
+  return 2.0 * p->v * p->v / ((kC / p->fc) * p->r_ref);
+}
+
+int cssar_params_with_rates(const cssar_params* in, double Ka, double Kr, cssar_params* out) {
+  if (!in || !out) return fail(CSSAR_EINVAL, "NULL parameters");
+  if (!(Ka > 0.0) || !(Kr > 0.0) || !std::isfinite(Ka) || !std::isfinite(Kr))
+    return fail(CSSAR_EINVAL, "the rates must be positive and finite");
+  if (!(in->fc > 0.0) || !(in->r_ref > 0.0)) return fail(CSSAR_EINVAL, "fc and r_ref must be positive");
+  const cssar_params p = *in;
+  *out = p;
+  out->v = std::sqrt(Ka * (kC / p.fc) * p.r_ref / 2.0);
+  out->Kr = Kr;
+  return CSSAR_OK;
+}
 
 int cssar_supported_length(int n) { return table_for(n) != nullptr; }
 
@@ -400,7 +451,7 @@ size_t cssar_workspace_size(const cssar_op* op, int mode) {
     case 0:
       return blk;
     case 1:
-      return 3 * blk;
+      return 3 * blk + sparse_layout(op).bytes;
     case 2:
       return 4 * blk + align256(support_bytes(op)) + align256(sizeof(AdaptState));
     case 3:
@@ -454,15 +505,14 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
   if (x_out == y || x_out == ws || ws == y) return fail(CSSAR_EINVAL, "x_out, y and ws must not alias");
   hipStream_t s = (hipStream_t)stream;
   const size_t blk = align256(b4_bytes(op->na, op->nr));
-  float2* X = (float2*)ws;                       // Xt = F_eta X (blocked layout)
+  float2* Xd = (float2*)ws;                      // dense tiles of the sparse iterate (blocked layout)
   float2* P = (float2*)((char*)ws + blk);        // pass buffer (in place)
   float2* Y = (float2*)((char*)ws + 2 * blk);    // m o y (blocked layout, unsampled marked)
-  auto col = [&](int which, const ColArgs& a) { return launch_col(op, which, a, s); };
-  auto row = [&](const RowArgs& a) { return launch_row(op, a, s); };
   ColArgs a = col_args(op);
   a.y = Y;
   a.mask = (const uint32_t*)mask_bits;
   a.sigma = lambda * a.mu;
+  set_sparse(op, a, Xd, (char*)ws + 3 * blk);
   for (int t = 0; t < iters; ++t) {
     const bool last = t == iters - 1;
     a.hist_out = resid_hist ? resid_hist + t : nullptr;
@@ -473,26 +523,28 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
       f.out = P;
       f.out2 = Y;
       f.flags = 1 | 4;
-      if ((rc = col(CK_FWD, f))) return rc;
+      if ((rc = launch_col(op, CK_FWD, f, s))) return rc;
       if ((rc = residual_total(op, CK_FWD, f, true, s))) return rc;
     } else {
-      // P = F_eta G X (row chain of G on Xt); then R = m o y - m o G X, P = F_eta R
-      if ((rc = row(row_args(op, X, P, 1)))) return rc;
+      // P = F_eta G X (row chain of G on F_eta X, which the update pass left
+      // in P); then R = m o y - m o G X, P = F_eta R
+      if ((rc = launch_row(op, row_args(op, P, P, 1), s))) return rc;
       ColArgs r = a;
       r.in0 = P;
       r.out = P;
-      if ((rc = col(CK_R, r))) return rc;
+      if ((rc = launch_col(op, CK_R, r, s))) return rc;
       if ((rc = residual_total(op, CK_R, r, last, s))) return rc;  // (the last one: non-finite check)
     }
     // P = F_eta M R (row chain of M)
-    if ((rc = row(row_args(op, P, P, 0)))) return rc;
+    if ((rc = launch_row(op, row_args(op, P, P, 0), s))) return rc;
+    // X+ = S(X + F_eta^-1 P / N_a): the sparse iterate, and F_eta X+ into P
+    // (or X+ into x_out in the last iteration)
     ColArgs u = a;
-    u.in0 = X;
     u.in1 = P;
-    u.out = last ? (float2*)x_out : X;
+    u.out = last ? (float2*)x_out : P;
     u.flags = (t == 0 ? 1 : 0) | (last ? 2 : 0);
     u.hist_out = nullptr;
-    if ((rc = col(CK_A, u))) return rc;
+    if ((rc = launch_col(op, CK_AS, u, s))) return rc;
   }
   return CSSAR_OK;
 }

@@ -72,8 +72,17 @@ int col_mode(int slot) {
     case SL_R:
       return CK_R;
     default:
-      return CK_A;
+      return CK_AS;
   }
+}
+
+// Grouped column kernel of a kind and its launcher (the sparse-iterate
+// update has its own slot in the table).
+const void* col_group_fn(const KernelTable* kt, int ck) {
+  return ck == CK_AS ? kt->col_group_as_fn : kt->col_group_fn[ck];
+}
+hipError_t launch_col_group(const KernelTable* kt, int ck, const GroupArgs& g, int grid, hipStream_t s) {
+  return ck == CK_AS ? kt->col_group_as(g, grid, s) : kt->col_group[ck](g, grid, s);
 }
 
 }  // namespace
@@ -121,7 +130,7 @@ void plan_slots(cssar_batch* b) {
         total += g.row ? op->na / sl.kt->LR : op->nr / sl.kt->C;
       }
       sl.total = total;
-      const void* fn = g.row ? sl.kt->row_group_fn : sl.kt->col_group_fn[col_mode(k)];
+      const void* fn = g.row ? sl.kt->row_group_fn : col_group_fn(sl.kt, col_mode(k));
       const int occ = occupancy(fn, g.row ? sl.kt->RT : sl.kt->CT);
       const int per_cu = c.per_cu > 0 ? std::min(c.per_cu, occ) : occ;
       sl.grid = grid_for(total, b->cus, per_cu);
@@ -166,11 +175,11 @@ int upload_tables(cssar_batch* b, const CallArgs& c, hipStream_t s) {
         const cssar_op* op = b->ops[si];
         start[q] = acc;
         acc += g.row ? op->na / sl.kt->LR : op->nr / sl.kt->C;
-        float2* X = (float2*)(c.ws + b->ws_off[si]);
+        float2* Xd = (float2*)(c.ws + b->ws_off[si]);
         float2* P = (float2*)(c.ws + b->ws_off[si] + b->blk[si]);
         float2* Y = (float2*)(c.ws + b->ws_off[si] + 2 * b->blk[si]);
         if (g.row) {
-          RowArgs a = k == SL_ROW_M ? row_args(op, P, P, 0) : row_args(op, X, P, 1);
+          RowArgs a = row_args(op, P, P, k == SL_ROW_M ? 0 : 1);
           std::memcpy(h + sl.args + q * sizeof(RowArgs), &a, sizeof a);
           continue;
         }
@@ -197,10 +206,11 @@ int upload_tables(cssar_batch* b, const CallArgs& c, hipStream_t s) {
           case SL_A_MID:
           case SL_A_LAST:
           case SL_A_ONLY:
-            a.in0 = X;
+            // the sparse iterate (laid out for this slot's plan) and F_eta X+ into P
             a.in1 = P;
             a.flags = (k == SL_A_FIRST || k == SL_A_ONLY ? 1 : 0) | (k == SL_A_LAST || k == SL_A_ONLY ? 2 : 0);
-            a.out = (k == SL_A_LAST || k == SL_A_ONLY) ? xo : X;
+            a.out = (k == SL_A_LAST || k == SL_A_ONLY) ? xo : P;
+            set_sparse(op, a, Xd, c.ws + b->ws_off[si] + 3 * b->blk[si], sl.kt);
             break;
         }
         std::memcpy(h + sl.args + q * sizeof(ColArgs), &a, sizeof a);
@@ -222,7 +232,7 @@ int launch_slot(cssar_batch* b, const Group& g, int k, hipStream_t s) {
   ga.count = (int)g.scenes.size();
   ga.total = sl.total;
   ga.conj = k == SL_ROW_G ? 1 : 0;  // (the row arguments of the slot carry the same)
-  hipError_t e = g.row ? sl.kt->row_group(ga, sl.grid, s) : sl.kt->col_group[col_mode(k)](ga, sl.grid, s);
+  hipError_t e = g.row ? sl.kt->row_group(ga, sl.grid, s) : launch_col_group(sl.kt, col_mode(k), ga, sl.grid, s);
   if (e != hipSuccess) return fail(CSSAR_EHIP, "grouped launch: %s", hipGetErrorString(e));
   return CSSAR_OK;
 }
@@ -352,13 +362,15 @@ int cssar_make_batch(cssar_op* const* ops, int count, cssar_batch** out) {
   b->arch = prop.gcnArchName;
   for (auto& ch : b->arch)
     if (ch == ' ') ch = '_';
-  // workspace: X, P, Y per scene
+  // workspace per scene: the dense tiles of the sparse iterate, P and Y
+  // (blocked arrays), then the sparse iterate (sized for the largest layout
+  // of the update plans the autotuner may pick)
   size_t off = 0;
   for (auto* op : b->ops) {
     const size_t blk = align256(b4_bytes(op->na, op->nr));
     b->ws_off.push_back(off);
     b->blk.push_back(blk);
-    off += 3 * blk;
+    off += 3 * blk + sparse_bytes_max(op);
   }
   b->ws_bytes = off;
   // groups by line length, scenes in batch order
@@ -387,7 +399,7 @@ int cssar_make_batch(cssar_op* const* ops, int count, cssar_batch** out) {
       continue;
     }
     for (int tk : {(int)TK_R, (int)TK_A}) {
-      const int v = column_variant(g.n, tk == TK_R ? CK_R : CK_A);
+      const int v = column_variant(g.n, tk == TK_R ? CK_R : CK_AS);
       const KernelTable* kt = table_for(g.n, v);
       if (kt && variant_fits(b, g, kt)) g.ch[tk].variant = v;
     }
@@ -524,7 +536,7 @@ int cssar_batch_autotune(cssar_batch* b, void* ws, const char* cache_path, void*
       for (int v = 0; v < kMaxVariants; ++v) {
         const KernelTable* kt = table_for(g.n, v);
         if (!kt || !variant_fits(b, g, kt)) continue;
-        const void* fn = g.row ? kt->row_group_fn : kt->col_group_fn[col_mode(slot)];
+        const void* fn = g.row ? kt->row_group_fn : col_group_fn(kt, col_mode(slot));
         const int occ = occupancy(fn, g.row ? kt->RT : kt->CT);
         for (int pc = 1; pc <= occ; ++pc) {
           g.ch[tk].variant = v;

@@ -112,6 +112,21 @@ int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s);
 int residual_total(cssar_op* op, int ck, const ColArgs& a, bool check, hipStream_t s);
 int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s);
 
+// Workspace of the sparse iterate after the solver's three blocked arrays:
+// byte offsets of the support words (0), the tile counts and the value
+// pool, the total, the tile count and the pool slots per tile.
+struct SparseLayout {
+  size_t count, pool, bytes;
+  int ntiles, cap;
+};
+// The layout for the update plan kt (NULL: the operator's own).
+SparseLayout sparse_layout(const cssar_op* op, const KernelTable* kt = nullptr);
+// The largest layout over the plan variants of length N_a (batched solver).
+size_t sparse_bytes_max(const cssar_op* op);
+// Points a's sparse-iterate fields at base (laid out by sparse_layout for
+// kt) and dense (a blocked array for the dense tiles).
+void set_sparse(const cssar_op* op, ColArgs& a, void* dense, void* base, const KernelTable* kt = nullptr);
+
 // Bytes of the support bits of the adaptive solver's column passes.
 size_t support_bytes(const cssar_op* op);
 

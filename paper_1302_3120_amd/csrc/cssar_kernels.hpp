@@ -94,10 +94,11 @@ struct RowArgs {
 // Column modes.  FWD, INV, A, R: the forward passes.  VB, U, XB: the
 // adjoint passes of the gradient (threshold adjoint, data adjoint, update
 // of the iterate's adjoint).
-// D, N, V, T: the passes of the adaptive step and threshold.
+// D, N, V, T: the passes of the adaptive step and threshold.  AS: the
+// update pass of the sparse iterate (col_update_sparse).
 enum ColMode {
   COL_FWD = 0, COL_INV = 1, COL_A = 2, COL_R = 3, COL_VB = 4, COL_U = 5, COL_XB = 6,
-  COL_D = 7, COL_N = 8, COL_V = 9, COL_T = 10
+  COL_D = 7, COL_N = 8, COL_V = 9, COL_T = 10, COL_AS = 11
 };
 
 // Device-resident state of the adaptive solver (one per solve, in its
@@ -128,6 +129,9 @@ struct AdaptState {
 // Marks an unsampled entry of the stored copy of m o y (real part; a NaN
 // with a payload that arithmetic does not produce).
 constexpr uint32_t kUnsampled = 0x7FA5A5A5u;
+
+// Count of a column tile of the sparse iterate whose X is stored densely.
+constexpr uint32_t kDenseTile = 0xFFFFFFFFu;
 
 struct ColArgs {
   const float2* in0;     // FWD: input (RM); INV: input (B4); A, VB: Xt (B4, NULL on the first
@@ -160,6 +164,15 @@ struct ColArgs {
   const uint32_t* supp_old;  // T: support bits of the iterate X (compared with X+'s)
   float2* out3;          // T with flag 16: X+ (spatial, row-major)
   const unsigned* gate;  // if not NULL, the pass does nothing while *gate == 0
+  // sparse iterate (AS): per column tile, the support word of every thread
+  // (word tile * CT + thread, bit k = element b + T k), the count of
+  // nonzeros (or kDenseTile), their values in (thread, k) order in xcap
+  // slots per tile, and the dense store of the tiles with more than xcap
+  uint32_t* xsupp;
+  uint32_t* xcount;
+  float2* xpool;
+  float2* xdense;        // B4
+  int xcap;
 };
 
 // Elementwise work on the E register elements in chunks of CH, with
@@ -746,7 +759,10 @@ constexpr bool col_pipelined() {
 }
 
 // Column passes whose twiddles come precomputed per thread (hoisted_pass,
-// table_pass): the update and residual passes of unsplit plans.
+// table_pass): the update and residual passes of unsplit plans.  (The
+// sparse-iterate update pass computes them per tile: its workgroup-wide
+// prefix sums would otherwise push it past 128 VGPRs, the limit of two
+// 512-thread workgroups per compute unit.)
 template <class P, int MODE>
 constexpr bool col_hoisted() {
   return (MODE == COL_A || MODE == COL_R) && hoisted_pass<P>() >= 0 && !P::SPLIT;
@@ -778,6 +794,106 @@ struct MaskAddr {
 __device__ __forceinline__ MaskAddr mask_addr(int b, int j, int T, int nr) {
   const uint32_t e0 = (((uint32_t)(b >> 2) * (nr / 4) + (j >> 2)) << 4) + ((b & 3) << 2) + (j & 3);
   return {(e0 >> 5) * 4u, e0 & 31u, (uint32_t)T * (uint32_t)nr / 32u * 4u};
+}
+
+// ------------------------------------------------ sparse-iterate update --
+// The update pass with the iterate X kept spatially and sparsely (the
+// thresholded iterate of a sparse scene has few nonzeros).  Per column tile:
+// the support word of every thread in xsupp (bit k: element b + T k of the
+// thread's column is nonzero), the nonzero values in (thread, k) order in
+// the tile's xcap slots of xpool, their count in xcount; a tile with more
+// than xcap nonzeros stores its X densely in xdense (B4) and the count
+// kDenseTile.
+//   V = F_eta^-1[Z] mu / N_a + X  ->  X+ = S_sigma(V)  ->  X+ (sparse) and
+//   F_eta X+ into out (B4, in place over Z: the next row pass of G reads
+//   it), or X+ row-major (flag 2: the last iteration; flag 1: X = 0).
+// It reads Z (8 B/pixel) and writes F_eta X+ (8 B/pixel) plus the support
+// words (E/8 B/pixel... 4 bytes per E elements each way) and the nonzeros,
+// against 24 B/pixel for the update of an azimuth-spectrum iterate.
+template <class P, bool HT>
+__device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, int b, int c, float2* lds,
+                                                  const float2* twl, const TwPowers& hp, uint32_t* scan) {
+  constexpr int HSC = HT ? hoisted_pass<P>() : -1;
+  constexpr int N = P::N, E = P::E, T = P::T, C = P::C, CT = P::CT;
+  static_assert(E <= 32, "support word holds E bits");
+  const uint32_t rmb = clamp_bytes((size_t)N * a.nr * 8), b4b = clamp_bytes(b4_bytes(N, a.nr));
+  const bool first = a.flags & 1, last = a.flags & 2;
+  const int j = tile * C + c;
+  const Addr ab = col_addr(B4, b, j, T, a.nr);
+  const Buf zin(a.in1, b4b), xd(a.xdense, b4b);
+  const Buf pool(a.xpool, clamp_bytes((size_t)(a.nr / C) * (size_t)a.xcap * 8));
+  const uint32_t word = (uint32_t)tile * CT + threadIdx.x;
+  const float ms = a.mu * a.scale;
+  float2 v[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) v[k] = cscale(zin.f2(ab.voff, k * ab.kstep), ms);
+  // the iterate's count (uniform) and support word go in flight with Z
+  uint32_t cnt_old = 0, m_old = 0;
+  if (!first) {
+    cnt_old = a.xcount[tile];
+    if (cnt_old != kDenseTile) m_old = a.xsupp[word];
+  }
+  const TwLds tws{twl, twl + 64};
+  int lb = b, lc = c;
+  asm volatile("" : "+v"(lb), "+v"(lc));  // recompute LDS addresses per tile
+  fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
+  // V = ... + X
+  if (!first) {
+    if (cnt_old == kDenseTile) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) v[k] = cadd(v[k], xd.f2(ab.voff, k * ab.kstep));
+    } else {
+      uint32_t tot;
+      uint32_t o = block_exscan<CT>(__builtin_popcount(m_old), scan, tot) + (uint32_t)tile * a.xcap;
+      if (tot > 0) {
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+          if ((m_old >> k) & 1u) {
+            v[k] = cadd(v[k], pool.f2(o * 8u, 0));
+            ++o;
+          }
+      }
+    }
+  }
+  // X+ = S_sigma(V) (the arithmetic of the azimuth-spectrum update pass)
+  const float s2 = a.sigma * a.sigma;
+  uint32_t m_new = 0;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const float m2 = fmaf(v[k].x, v[k].x, v[k].y * v[k].y);
+    const float f = m2 > s2 ? fmaf(-a.sigma, rsqrtf(m2), 1.0f) : 0.0f;
+    v[k] = cscale(v[k], f);
+    m_new |= (v[k].x != 0.f || v[k].y != 0.f ? 1u : 0u) << k;
+  }
+  if (last) {
+    const Buf out(a.out, rmb);
+    const Addr ar = col_addr(RM, b, j, T, a.nr);
+#pragma unroll
+    for (int k = 0; k < E; ++k) out.st(v[k], ar.voff, k * ar.kstep);
+    return;
+  }
+  uint32_t tot;
+  const uint32_t off = block_exscan<CT>(__builtin_popcount(m_new), scan, tot);
+  if (tot <= (uint32_t)a.xcap) {
+    a.xsupp[word] = m_new;
+    uint32_t o = off + (uint32_t)tile * a.xcap;
+#pragma unroll
+    for (int k = 0; k < E; ++k)
+      if ((m_new >> k) & 1u) {
+        pool.st(v[k], o * 8u, 0);
+        ++o;
+      }
+    if (threadIdx.x == 0) a.xcount[tile] = tot;
+  } else {
+#pragma unroll
+    for (int k = 0; k < E; ++k) xd.st(v[k], ab.voff, k * ab.kstep);
+    if (threadIdx.x == 0) a.xcount[tile] = kDenseTile;
+  }
+  asm volatile("" : "+v"(lb), "+v"(lc));
+  fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);  // F_eta X+
+  const Buf out(a.out, b4b);
+#pragma unroll
+  for (int k = 0; k < E; ++k) out.st(v[k], ab.voff, k * ab.kstep);
 }
 
 // HT: the twiddles of the passes a thread can precompute come from hp
@@ -1075,6 +1191,7 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   float acc = 0.f;
   unsigned chg = 0u;
   float2 pre[P::E];
+  __shared__ uint32_t scan[MODE == COL_AS ? CT / 64 : 1];
   // the value pass (adaptive threshold) also counts the first selection level
   __shared__ unsigned hist0[MODE == COL_V ? 2048 : 1];
   if constexpr (MODE == COL_V) {
@@ -1087,7 +1204,8 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   }
   for (; tile < ntiles; tile += gridDim.x) {
     const int next = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : -1;
-    acc += col_unit<P, MODE, PIPE, HT>(a, tile, b, c, lds, twl, pre, next, hp, hist0, &chg);
+    if constexpr (MODE == COL_AS) col_update_sparse<P, HT>(a, tile, b, c, lds, twl, hp, scan);
+    else acc += col_unit<P, MODE, PIPE, HT>(a, tile, b, c, lds, twl, pre, next, hp, hist0, &chg);
   }
   if constexpr (MODE == COL_V) {
     __syncthreads();
@@ -1150,13 +1268,15 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_group_kern
   const int c = threadIdx.x % C;
   const int b = threadIdx.x / C;
   float2 pre[P::E];
+  __shared__ uint32_t scan[MODE == COL_AS ? P::CT / 64 : 1];
   // same per-line arithmetic as the single-array kernel (bit-identical results)
   constexpr bool HT = col_hoisted<P, MODE>();
   TwPowers hp;
   if constexpr (HT) hp = hoist_powers<P>(b, TwLds{twl, twl + 64}, ptab);
   for (int u = xcd_logical_block(); u < g.total; u += gridDim.x) {
     const int s = group_find(g.start, g.count, u);
-    (void)col_unit<P, MODE, false, HT>(args[s], u - g.start[s], b, c, lds, twl, pre, -1, hp);
+    if constexpr (MODE == COL_AS) col_update_sparse<P, HT>(args[s], u - g.start[s], b, c, lds, twl, hp, scan);
+    else (void)col_unit<P, MODE, false, HT>(args[s], u - g.start[s], b, c, lds, twl, pre, -1, hp);
   }
 }
 

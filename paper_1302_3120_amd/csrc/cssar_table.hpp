@@ -12,9 +12,11 @@ struct RowArgs;
 struct ColArgs;
 struct GroupArgs;
 
-// Column kernels: the first CK_GROUPED also exist as grouped (batched) kernels.
-// CK_D .. CK_T: the adaptive step and threshold passes.
-enum ColKernel { CK_FWD = 0, CK_INV, CK_A, CK_R, CK_VB, CK_U, CK_XB, CK_D, CK_N, CK_V, CK_T, CK_COUNT };
+// Column kernels (the same order as ColMode): the first CK_GROUPED also
+// exist as grouped (batched) kernels, and so does CK_AS (col_group_as).
+// CK_D .. CK_T: the adaptive step and threshold passes; CK_AS: the update
+// pass of the sparse iterate.
+enum ColKernel { CK_FWD = 0, CK_INV, CK_A, CK_R, CK_VB, CK_U, CK_XB, CK_D, CK_N, CK_V, CK_T, CK_AS, CK_COUNT };
 constexpr int CK_GROUPED = 4;
 
 struct KernelTable {
@@ -24,12 +26,14 @@ struct KernelTable {
   hipError_t (*col[CK_COUNT])(const ColArgs&, int, hipStream_t);
   hipError_t (*row_group)(const GroupArgs&, int, hipStream_t);
   hipError_t (*col_group[CK_GROUPED])(const GroupArgs&, int, hipStream_t);
+  hipError_t (*col_group_as)(const GroupArgs&, int, hipStream_t);
   hipError_t (*row_adj[2])(const RowArgs&, int, hipStream_t);  // forward chain M (0) or G (1)
   hipError_t (*row_rda[2])(const RowArgs&, int, hipStream_t);  // range-Doppler chain M (0), G (1)
   const void* row_fn;
   const void* col_fn[CK_COUNT];
   const void* row_group_fn;
   const void* col_group_fn[CK_GROUPED];
+  const void* col_group_as_fn;
   const void* row_adj_fn[2];
   const void* row_rda_fn[2];
 };

@@ -24,10 +24,11 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
       {&K::template col<COL_FWD>, &K::template col<COL_INV>, &K::template col<COL_A>,
        &K::template col<COL_R>, &K::template col<COL_VB>, &K::template col<COL_U>,
        &K::template col<COL_XB>, &K::template col<COL_D>, &K::template col<COL_N>,
-       &K::template col<COL_V>, &K::template col<COL_T>},
+       &K::template col<COL_V>, &K::template col<COL_T>, &K::template col<COL_AS>},
       &K::row_group,
       {&K::template col_group<COL_FWD>, &K::template col_group<COL_INV>,
        &K::template col_group<COL_A>, &K::template col_group<COL_R>},
+      &K::template col_group<COL_AS>,
       {&K::template row_adj<0>, &K::template row_adj<1>},
       {&K::template row_rda<0>, &K::template row_rda<1>},
       reinterpret_cast<const void*>(&row_pass_kernel<P, 0>),
@@ -41,12 +42,14 @@ const KernelTable* CSSAR_TABLE_NAME(CSSAR_N, CSSAR_V)() {
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_D>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_N>),
        reinterpret_cast<const void*>(&col_pass_kernel<P, COL_V>),
-       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_T>)},
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_T>),
+       reinterpret_cast<const void*>(&col_pass_kernel<P, COL_AS>)},
       reinterpret_cast<const void*>(&row_group_kernel<P, 0>),
       {reinterpret_cast<const void*>(&col_group_kernel<P, COL_FWD>),
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_INV>),
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_A>),
        reinterpret_cast<const void*>(&col_group_kernel<P, COL_R>)},
+      reinterpret_cast<const void*>(&col_group_kernel<P, COL_AS>),
       {reinterpret_cast<const void*>(&row_adj_kernel<P, 0>),
        reinterpret_cast<const void*>(&row_adj_kernel<P, 1>)},
       {reinterpret_cast<const void*>(&row_rda_kernel<P, 0, 8>),

@@ -29,13 +29,14 @@ SYMBOLS = (
     "cssar_ita_solve_batched", "cssar_checkpoint_size", "cssar_grad_workspace_size",
     "cssar_ita_forward", "cssar_ita_backward", "cssar_ita_solve_adaptive",
     "cssar_make_operator_rda", "cssar_operator_chain", "cssar_ita_solve_safeguarded",
+    "cssar_azimuth_fm_rate", "cssar_params_with_rates",
 )
 
 PROFILE_KINDS = ("row_M", "row_G", "col_fwd", "col_inv", "col_update_threshold",
                  "col_residual", "col_threshold_adjoint", "col_data_adjoint",
                  "col_iterate_adjoint", "col_restricted_step", "col_step_norm",
                  "col_value", "col_threshold_selected", "row_adjoint_M", "row_adjoint_G",
-                 "select_kth")
+                 "select_kth", "col_update_sparse")
 NK = len(PROFILE_KINDS)
 
 
@@ -73,6 +74,11 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, i, f = ctypes.c_void_p, ctypes.c_int, ctypes.c_float
         L.cssar_make_operator.argtypes = [ctypes.POINTER(Params), i, i, ctypes.POINTER(vp)]
+        L.cssar_azimuth_fm_rate.argtypes = [ctypes.POINTER(Params)]
+        L.cssar_azimuth_fm_rate.restype = ctypes.c_double
+        L.cssar_params_with_rates.argtypes = [ctypes.POINTER(Params), ctypes.c_double, ctypes.c_double,
+                                              ctypes.POINTER(Params)]
+        L.cssar_params_with_rates.restype = ctypes.c_int
         L.cssar_make_operator_rda.argtypes = [ctypes.POINTER(Params), i, i, i, ctypes.POINTER(vp)]
         L.cssar_make_operator_rda.restype = ctypes.c_int
         L.cssar_operator_chain.argtypes = [vp]
@@ -416,32 +422,50 @@ def make_batch(ops):
     return Batch(ops)
 
 
-C_LIGHT = 299792458.0
+_PARAM_KEYS = ("fc", "Kr", "Tp", "fs", "prf", "v", "r_ref", "ba", "f_dc", "src")
 
 
 def ka_of(params):
-    """Azimuth FM rate at the reference range, K_a = 2 v^2 / (lambda_w r_ref)."""
-    return 2.0 * params["v"] ** 2 / ((C_LIGHT / params["fc"]) * params["r_ref"])
+    """Azimuth FM rate at the reference range (cssar_azimuth_fm_rate)."""
+    p = Params.from_dict(params)
+    return float(lib().cssar_azimuth_fm_rate(ctypes.byref(p)))
 
 
 def params_with_theta(params, Ka, Kr):
-    """params with v set from K_a and the range chirp rate set to K_r."""
+    """params with the azimuth FM rate Ka and the range chirp rate Kr
+    (cssar_params_with_rates)."""
+    src = Params.from_dict(params)
+    out = Params()
+    _check(lib().cssar_params_with_rates(ctypes.byref(src), float(Ka), float(Kr), ctypes.byref(out)))
     p = dict(params)
-    p["v"] = (Ka * (C_LIGHT / p["fc"]) * p["r_ref"] / 2.0) ** 0.5
-    p["Kr"] = float(Kr)
+    p.update({k: getattr(out, k) for k in _PARAM_KEYS})
     return p
+
+
+# The operator of the last ITAUnrolled call, reused while the parameters,
+# rates, shape and device stay the same.
+_unrolled_op = {"key": None, "op": None}
+
+
+def _unrolled_operator(params, Ka, Kr, shape, device):
+    key = (tuple(sorted((k, float(v)) for k, v in params.items() if k in _PARAM_KEYS)),
+           float(Ka), float(Kr), tuple(shape), str(device))
+    if _unrolled_op["key"] != key:
+        _unrolled_op["op"] = Operator(params_with_theta(params, float(Ka), float(Kr)), tuple(shape))
+        _unrolled_op["key"] = key
+    return _unrolled_op["op"]
 
 
 class ITAUnrolled(torch.autograd.Function):
     """X^(K) of K unrolled iterations as a differentiable function of the
     raw data y (complex64), lambda, K_a and K_r (0-dim float64 tensors).
     Forward: cssar_ita_forward with a checkpoint every ``every`` iterations;
-    backward: cssar_ita_backward.  The operator is rebuilt from (K_a, K_r)."""
+    backward: cssar_ita_backward.  The operator is built from (K_a, K_r) and
+    reused while they (and the other parameters) do not change."""
 
     @staticmethod
     def forward(ctx, y, lam, Ka, Kr, mask, iters, every, params):
-        p = params_with_theta(params, float(Ka), float(Kr))
-        op = Operator(p, tuple(y.shape))
+        op = _unrolled_operator(params, Ka, Kr, y.shape, y.device)
         bits = op.pack_mask(mask)
         x, ckpt = op.ita_forward(y.contiguous(), bits, float(lam), int(iters), int(every))
         ctx.op, ctx.bits, ctx.ckpt = op, bits, ckpt
