@@ -167,6 +167,21 @@ int cssar_pack_mask(const cssar_op* op, const void* mask_bytes, void* mask_bits,
 int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda,
                     int iters, void* x_out, float* resid_hist, void* ws, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid allocation): cssar_ita_solve with its
+ * workspace in a fixed device array of the library, CSSAR_STATIC_WORKSPACE_BYTES
+ * per device, which each device holds from the library's load until the
+ * process ends; the call allocates nothing.  Arguments as cssar_ita_solve,
+ * without ws.  CSSAR_EINVAL when the solve needs a larger workspace
+ * (cssar_workspace_size(op, 1) > CSSAR_STATIC_WORKSPACE_BYTES: beyond about
+ * 1536 x 1536 pixels), when the current device is not the operator's, or
+ * while per-launch timing is enabled (it creates events).  Every call on a
+ * device shares that device's array: calls that overlap on one device (on two
+ * streams, or from two host threads) race and corrupt each other's results. */
+#define CSSAR_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int cssar_ita_solve_static(cssar_op* op, const void* y, const void* mask_bits, float lambda,
+                           int iters, void* x_out, float* resid_hist, void* stream);
+
 /* Iterative thresholding with both parameters set per iteration as Section
  * IV.B suggests (eq. (mure) and the threshold rule after it):
  *   R = m o (y - G X);  dX = M R;

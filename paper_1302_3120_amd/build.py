@@ -61,7 +61,8 @@ def build(jobs=None, verbose=False, report=False):
         obj = os.path.join(BUILD, f"kern_{n}_{v}.o")
         cmds.append([cc, *flags, *extra, f"-DCSSAR_N={n}", f"-DCSSAR_V={v}", "-c",
                      os.path.join(CSRC, "kern_inst.hip"), "-o", obj])
-    for src in ("cssar_api.hip", "cssar_batch.hip", "cssar_grad.hip", "cssar_adaptive.hip"):
+    for src in ("cssar_api.hip", "cssar_batch.hip", "cssar_grad.hip", "cssar_adaptive.hip",
+                "cssar_noalloc.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         cmds.append([cc, *flags, "-c", os.path.join(CSRC, src), "-o", obj])
     jobs = jobs or min(len(cmds), max(1, os.cpu_count() or 1))
