@@ -216,14 +216,9 @@ int launch_col(cssar_op* op, int which, const ColArgs& a, hipStream_t s) {
 SparseLayout sparse_layout(const cssar_op* op, const KernelTable* kt) {
   if (!kt) kt = op->kcol[CK_AS];
   SparseLayout L;
-  L.ntiles = op->nr / kt->C;
-  L.cap = kt->CT * kt->E / 4;  // a quarter of the tile
-  size_t o = align256((size_t)L.ntiles * kt->CT * 4);
-  L.count = o;
-  o += align256((size_t)L.ntiles * 4);
-  L.pool = o;
-  o += align256((size_t)L.ntiles * L.cap * 8);
-  L.bytes = o;
+  const size_t ntiles = (size_t)(op->nr / kt->C);
+  L.slots = align256(ntiles * kt->CT * 4);           // after the support words
+  L.bytes = L.slots + align256(ntiles * kt->CT * 16);  // one float4 slot per thread
   return L;
 }
 
@@ -238,12 +233,9 @@ size_t sparse_bytes_max(const cssar_op* op) {
 
 void set_sparse(const cssar_op* op, ColArgs& a, void* dense, void* base, const KernelTable* kt) {
   const SparseLayout L = sparse_layout(op, kt);
-  char* b = (char*)base;
-  a.xsupp = (uint32_t*)b;
-  a.xcount = (uint32_t*)(b + L.count);
-  a.xpool = (float2*)(b + L.pool);
+  a.xsupp = (uint32_t*)base;
+  a.xslots = (float4*)((char*)base + L.slots);
   a.xdense = (float2*)dense;
-  a.xcap = L.cap;
 }
 
 // ||R||^2 of the residual pass (or ||m o y||^2 of the first forward pass)

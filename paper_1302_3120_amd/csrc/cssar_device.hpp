@@ -555,36 +555,4 @@ __device__ __forceinline__ float block_sum(float x, float* red) {
   return s;
 }
 
-// Exclusive prefix sum over the workgroup (NT threads, in thread order) of
-// one count x < 64 per thread, and the total (in every thread).  Within a
-// wave the sum is taken bit plane by bit plane (a ballot of bit p and the
-// count of set lanes below this one), which keeps it in scalar registers;
-// tmp: NT/64 words of LDS for the wave totals, reusable when it returns
-// (two barriers).
-template <int NT>
-__device__ __forceinline__ uint32_t block_exscan(uint32_t x, uint32_t* tmp, uint32_t& total) {
-  const int wid = threadIdx.x >> 6;
-  uint32_t pre = 0, wtot = 0;
-#pragma unroll
-  for (int p = 0; p < 6; ++p) {
-    const unsigned long long bal = __ballot((x >> p) & 1u);
-    const uint32_t below =
-        __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-    pre += below << p;
-    wtot += (uint32_t)__builtin_popcountll(bal) << p;
-  }
-  if ((threadIdx.x & 63) == 0) tmp[wid] = wtot;
-  __syncthreads();
-  uint32_t before = 0, all = 0;
-#pragma unroll
-  for (int w = 0; w < NT / 64; ++w) {
-    const uint32_t t = tmp[w];
-    before += w < wid ? t : 0u;
-    all += t;
-  }
-  __syncthreads();
-  total = all;
-  return before + pre;
-}
-
 }  // namespace cssar

@@ -130,9 +130,6 @@ struct AdaptState {
 // with a payload that arithmetic does not produce).
 constexpr uint32_t kUnsampled = 0x7FA5A5A5u;
 
-// Count of a column tile of the sparse iterate whose X is stored densely.
-constexpr uint32_t kDenseTile = 0xFFFFFFFFu;
-
 struct ColArgs {
   const float2* in0;     // FWD: input (RM); INV: input (B4); A, VB: Xt (B4, NULL on the first
                          // iteration); R: W (B4); U: F G Vbar; XB: F M ubar
@@ -165,14 +162,13 @@ struct ColArgs {
   float2* out3;          // T with flag 16: X+ (spatial, row-major)
   const unsigned* gate;  // if not NULL, the pass does nothing while *gate == 0
   // sparse iterate (AS): per column tile, the support word of every thread
-  // (word tile * CT + thread, bit k = element b + T k), the count of
-  // nonzeros (or kDenseTile), their values in (thread, k) order in xcap
-  // slots per tile, and the dense store of the tiles with more than xcap
+  // (word tile * CT + thread, bit k = element b + T k; kDenseWord: the
+  // thread's elements are in xdense), its slot (the first two nonzero
+  // values, float4 index tile * CT + thread) and the dense store of the
+  // threads with more than two nonzeros
   uint32_t* xsupp;
-  uint32_t* xcount;
-  float2* xpool;
+  float4* xslots;
   float2* xdense;        // B4
-  int xcap;
 };
 
 // Elementwise work on the E register elements in chunks of CH, with
@@ -754,18 +750,16 @@ __global__ __launch_bounds__(P::RT) void row_adj_kernel(RowArgs a) {
 // workgroup instead.
 template <class P, int MODE>
 constexpr bool col_pipelined() {
-  return (MODE == COL_A || (MODE == COL_R && P::E >= 32 && P::C >= 4) || MODE == COL_D || MODE == COL_N) &&
+  return (MODE == COL_A || ((MODE == COL_R || MODE == COL_AS) && P::E >= 32 && P::C >= 4) || MODE == COL_D ||
+          MODE == COL_N) &&
          !P::SPLIT;
 }
 
 // Column passes whose twiddles come precomputed per thread (hoisted_pass,
-// table_pass): the update and residual passes of unsplit plans.  (The
-// sparse-iterate update pass computes them per tile: its workgroup-wide
-// prefix sums would otherwise push it past 128 VGPRs, the limit of two
-// 512-thread workgroups per compute unit.)
+// table_pass): the update and residual passes of unsplit plans.
 template <class P, int MODE>
 constexpr bool col_hoisted() {
-  return (MODE == COL_A || MODE == COL_R) && hoisted_pass<P>() >= 0 && !P::SPLIT;
+  return (MODE == COL_A || MODE == COL_AS || MODE == COL_R) && hoisted_pass<P>() >= 0 && !P::SPLIT;
 }
 
 template <class P, int MODE>
@@ -782,6 +776,10 @@ __device__ __forceinline__ void col_preload(const ColArgs& a, int tile, int b, i
     const Buf in0(a.in0, b4b);
 #pragma unroll
     for (int k = 0; k < E; ++k) pre[k] = in0.f2(ab.voff, k * ab.kstep);
+  } else if constexpr (MODE == COL_AS) {
+    const Buf in1(a.in1, b4b);
+#pragma unroll
+    for (int k = 0; k < E; ++k) pre[k] = in1.f2(ab.voff, k * ab.kstep);
   }
 }
 
@@ -798,21 +796,26 @@ __device__ __forceinline__ MaskAddr mask_addr(int b, int j, int T, int nr) {
 
 // ------------------------------------------------ sparse-iterate update --
 // The update pass with the iterate X kept spatially and sparsely (the
-// thresholded iterate of a sparse scene has few nonzeros).  Per column tile:
-// the support word of every thread in xsupp (bit k: element b + T k of the
-// thread's column is nonzero), the nonzero values in (thread, k) order in
-// the tile's xcap slots of xpool, their count in xcount; a tile with more
-// than xcap nonzeros stores its X densely in xdense (B4) and the count
-// kDenseTile.
+// thresholded iterate of a sparse scene has few nonzeros).  Each thread of a
+// column tile owns E elements of X (b + T k, k < E, of its column) and keeps
+// them as one support word (bit k: element k is nonzero) and its first two
+// nonzero values, in rank order, in its own 16-byte slot; a thread with more
+// nonzeros stores its E values densely in xdense (B4) and the word
+// kDenseWord.  No thread reads another's data, so the pass needs no
+// workgroup-wide step, and the word and the slot go in flight with Z.
 //   V = F_eta^-1[Z] mu / N_a + X  ->  X+ = S_sigma(V)  ->  X+ (sparse) and
 //   F_eta X+ into out (B4, in place over Z: the next row pass of G reads
 //   it), or X+ row-major (flag 2: the last iteration; flag 1: X = 0).
-// It reads Z (8 B/pixel) and writes F_eta X+ (8 B/pixel) plus the support
-// words (E/8 B/pixel... 4 bytes per E elements each way) and the nonzeros,
-// against 24 B/pixel for the update of an azimuth-spectrum iterate.
-template <class P, bool HT>
+// Bytes per pixel: Z read and F_eta X+ written (16), the word read and
+// written (8/E), the slot read (16/E) and written where nonzero.
+constexpr uint32_t kDenseWord = 0xFFFFFFFFu;  // (no sparse word has more than two bits)
+
+// PIPE: Z of this tile was loaded into pre during the previous tile, and Z
+// of the next tile (next >= 0) is loaded into pre during this one.
+template <class P, bool HT, bool PIPE>
 __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, int b, int c, float2* lds,
-                                                  const float2* twl, const TwPowers& hp, uint32_t* scan) {
+                                                  const float2* twl, const TwPowers& hp,
+                                                  float2 (&pre)[P::E], int next) {
   constexpr int HSC = HT ? hoisted_pass<P>() : -1;
   constexpr int N = P::N, E = P::E, T = P::T, C = P::C, CT = P::CT;
   static_assert(E <= 32, "support word holds E bits");
@@ -821,49 +824,67 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
   const int j = tile * C + c;
   const Addr ab = col_addr(B4, b, j, T, a.nr);
   const Buf zin(a.in1, b4b), xd(a.xdense, b4b);
-  const Buf pool(a.xpool, clamp_bytes((size_t)(a.nr / C) * (size_t)a.xcap * 8));
+  const uint32_t ntiles = (uint32_t)(a.nr / C);
+  const Buf slots(a.xslots, clamp_bytes((size_t)ntiles * CT * 16));
   const uint32_t word = (uint32_t)tile * CT + threadIdx.x;
+  // the iterate's support word and slot, then Z
+  uint32_t m_old = 0;
+  float4 s01 = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (!first) {
+    m_old = a.xsupp[word];
+    s01 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots.r, word * 16u, 0, 0));
+  }
   const float ms = a.mu * a.scale;
   float2 v[E];
 #pragma unroll
-  for (int k = 0; k < E; ++k) v[k] = cscale(zin.f2(ab.voff, k * ab.kstep), ms);
-  // the iterate's count (uniform) and support word go in flight with Z
-  uint32_t cnt_old = 0, m_old = 0;
-  if (!first) {
-    cnt_old = a.xcount[tile];
-    if (cnt_old != kDenseTile) m_old = a.xsupp[word];
+  for (int k = 0; k < E; ++k) v[k] = cscale(PIPE ? pre[k] : zin.f2(ab.voff, k * ab.kstep), ms);
+  if constexpr (PIPE) {
+    if (next >= 0) col_preload<P, COL_AS>(a, next, b, c, pre);
   }
   const TwLds tws{twl, twl + 64};
   int lb = b, lc = c;
   asm volatile("" : "+v"(lb), "+v"(lc));  // recompute LDS addresses per tile
   fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
-  // V = ... + X
-  if (!first) {
-    if (cnt_old == kDenseTile) {
+  // V = ... + X.  Nonzeros are rare, so each element's addition and capture
+  // below run only where some lane of the wave needs them (a wave-uniform
+  // branch on the ballot), not as selects in every lane.
+  if (m_old == kDenseWord) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) v[k] = cadd(v[k], xd.f2(ab.voff, k * ab.kstep));
-    } else {
-      uint32_t tot;
-      uint32_t o = block_exscan<CT>(__builtin_popcount(m_old), scan, tot) + (uint32_t)tile * a.xcap;
-      if (tot > 0) {
+    for (int k = 0; k < E; ++k) v[k] = cadd(v[k], xd.f2(ab.voff, k * ab.kstep));
+  } else {
+    const uint32_t k0 = m_old & (0u - m_old);  // lowest set bit: the first slot
 #pragma unroll
-        for (int k = 0; k < E; ++k)
-          if ((m_old >> k) & 1u) {
-            v[k] = cadd(v[k], pool.f2(o * 8u, 0));
-            ++o;
-          }
+    for (int k = 0; k < E; ++k) {
+      const bool bit = (m_old >> k) & 1u;
+      if (__ballot(bit)) {
+        const float2 x = (k0 >> k) & 1u ? make_float2(s01.x, s01.y) : make_float2(s01.z, s01.w);
+        if (bit) v[k] = cadd(v[k], x);
       }
     }
   }
-  // X+ = S_sigma(V) (the arithmetic of the azimuth-spectrum update pass)
+  // X+ = S_sigma(V) (the arithmetic of the azimuth-spectrum update pass);
+  // the support and the first two nonzeros as they come
   const float s2 = a.sigma * a.sigma;
   uint32_t m_new = 0;
+  float4 x01 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const float m2 = fmaf(v[k].x, v[k].x, v[k].y * v[k].y);
-    const float f = m2 > s2 ? fmaf(-a.sigma, rsqrtf(m2), 1.0f) : 0.0f;
+    const bool keep = m2 > s2;
+    const float f = keep ? fmaf(-a.sigma, rsqrtf(m2), 1.0f) : 0.0f;
     v[k] = cscale(v[k], f);
-    m_new |= (v[k].x != 0.f || v[k].y != 0.f ? 1u : 0u) << k;
+    if (__ballot(keep)) {
+      if (keep) {
+        if (m_new == 0u) {
+          x01.x = v[k].x;
+          x01.y = v[k].y;
+        } else {
+          x01.z = v[k].x;
+          x01.w = v[k].y;
+        }
+        m_new |= 1u << k;
+      }
+    }
   }
   if (last) {
     const Buf out(a.out, rmb);
@@ -872,22 +893,16 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
     for (int k = 0; k < E; ++k) out.st(v[k], ar.voff, k * ar.kstep);
     return;
   }
-  uint32_t tot;
-  const uint32_t off = block_exscan<CT>(__builtin_popcount(m_new), scan, tot);
-  if (tot <= (uint32_t)a.xcap) {
+  if (__builtin_popcount(m_new) <= 2) {
     a.xsupp[word] = m_new;
-    uint32_t o = off + (uint32_t)tile * a.xcap;
-#pragma unroll
-    for (int k = 0; k < E; ++k)
-      if ((m_new >> k) & 1u) {
-        pool.st(v[k], o * 8u, 0);
-        ++o;
-      }
-    if (threadIdx.x == 0) a.xcount[tile] = tot;
+    if (m_new) {
+      using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(slots.r, 0u, 0u, 0));
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, x01), slots.r, word * 16u, 0, 0);
+    }
   } else {
+    a.xsupp[word] = kDenseWord;
 #pragma unroll
     for (int k = 0; k < E; ++k) xd.st(v[k], ab.voff, k * ab.kstep);
-    if (threadIdx.x == 0) a.xcount[tile] = kDenseTile;
   }
   asm volatile("" : "+v"(lb), "+v"(lc));
   fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);  // F_eta X+
@@ -1191,7 +1206,6 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   float acc = 0.f;
   unsigned chg = 0u;
   float2 pre[P::E];
-  __shared__ uint32_t scan[MODE == COL_AS ? CT / 64 : 1];
   // the value pass (adaptive threshold) also counts the first selection level
   __shared__ unsigned hist0[MODE == COL_V ? 2048 : 1];
   if constexpr (MODE == COL_V) {
@@ -1204,7 +1218,7 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   }
   for (; tile < ntiles; tile += gridDim.x) {
     const int next = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : -1;
-    if constexpr (MODE == COL_AS) col_update_sparse<P, HT>(a, tile, b, c, lds, twl, hp, scan);
+    if constexpr (MODE == COL_AS) col_update_sparse<P, HT, PIPE>(a, tile, b, c, lds, twl, hp, pre, next);
     else acc += col_unit<P, MODE, PIPE, HT>(a, tile, b, c, lds, twl, pre, next, hp, hist0, &chg);
   }
   if constexpr (MODE == COL_V) {
@@ -1268,14 +1282,14 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_group_kern
   const int c = threadIdx.x % C;
   const int b = threadIdx.x / C;
   float2 pre[P::E];
-  __shared__ uint32_t scan[MODE == COL_AS ? P::CT / 64 : 1];
   // same per-line arithmetic as the single-array kernel (bit-identical results)
   constexpr bool HT = col_hoisted<P, MODE>();
   TwPowers hp;
   if constexpr (HT) hp = hoist_powers<P>(b, TwLds{twl, twl + 64}, ptab);
   for (int u = xcd_logical_block(); u < g.total; u += gridDim.x) {
     const int s = group_find(g.start, g.count, u);
-    if constexpr (MODE == COL_AS) col_update_sparse<P, HT>(args[s], u - g.start[s], b, c, lds, twl, hp, scan);
+    if constexpr (MODE == COL_AS)
+      col_update_sparse<P, HT, false>(args[s], u - g.start[s], b, c, lds, twl, hp, pre, -1);
     else (void)col_unit<P, MODE, false, HT>(args[s], u - g.start[s], b, c, lds, twl, pre, -1, hp);
   }
 }
