@@ -217,8 +217,8 @@ SparseLayout sparse_layout(const cssar_op* op, const KernelTable* kt) {
   if (!kt) kt = op->kcol[CK_AS];
   SparseLayout L;
   const size_t ntiles = (size_t)(op->nr / kt->C);
-  L.slots = align256(ntiles * kt->CT * 4);           // after the support words
-  L.bytes = L.slots + align256(ntiles * kt->CT * 16);  // one float4 slot per thread
+  L.wmask = align256(ntiles * kt->CT * 32);             // after the 32-byte records
+  L.bytes = L.wmask + align256(ntiles * (kt->CT / 64) * 8);  // one 8-byte mask per wave
   return L;
 }
 
@@ -233,8 +233,8 @@ size_t sparse_bytes_max(const cssar_op* op) {
 
 void set_sparse(const cssar_op* op, ColArgs& a, void* dense, void* base, const KernelTable* kt) {
   const SparseLayout L = sparse_layout(op, kt);
-  a.xsupp = (uint32_t*)base;
-  a.xslots = (float4*)((char*)base + L.slots);
+  a.xrec = (float4*)base;
+  a.xwmask = (uint64_t*)((char*)base + L.wmask);
   a.xdense = (float2*)dense;
 }
 

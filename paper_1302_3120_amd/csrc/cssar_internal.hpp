@@ -113,10 +113,10 @@ int residual_total(cssar_op* op, int ck, const ColArgs& a, bool check, hipStream
 int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s);
 
 // Workspace of the sparse iterate after the solver's three blocked arrays:
-// the support words (from byte 0), the byte offset of the value slots, and
+// the thread records (from byte 0), the byte offset of the wave masks, and
 // the total.
 struct SparseLayout {
-  size_t slots, bytes;
+  size_t wmask, bytes;
 };
 // The layout for the update plan kt (NULL: the operator's own).
 SparseLayout sparse_layout(const cssar_op* op, const KernelTable* kt = nullptr);

@@ -161,13 +161,12 @@ struct ColArgs {
   const uint32_t* supp_old;  // T: support bits of the iterate X (compared with X+'s)
   float2* out3;          // T with flag 16: X+ (spatial, row-major)
   const unsigned* gate;  // if not NULL, the pass does nothing while *gate == 0
-  // sparse iterate (AS): per column tile, the support word of every thread
-  // (word tile * CT + thread, bit k = element b + T k; kDenseWord: the
-  // thread's elements are in xdense), its slot (the first two nonzero
-  // values, float4 index tile * CT + thread) and the dense store of the
-  // threads with more than two nonzeros
-  uint32_t* xsupp;
-  float4* xslots;
+  // sparse iterate (AS, col_update_sparse): per column tile, the 32-byte
+  // record of every thread with nonzeros (index tile * CT + thread), the
+  // 64-bit lane mask of every wave (index tile * CT/64 + wave), and the dense
+  // store of the threads with more than two nonzeros
+  float4* xrec;
+  uint64_t* xwmask;
   float2* xdense;        // B4
 };
 
@@ -797,18 +796,28 @@ __device__ __forceinline__ MaskAddr mask_addr(int b, int j, int T, int nr) {
 // ------------------------------------------------ sparse-iterate update --
 // The update pass with the iterate X kept spatially and sparsely (the
 // thresholded iterate of a sparse scene has few nonzeros).  Each thread of a
-// column tile owns E elements of X (b + T k, k < E, of its column) and keeps
-// them as one support word (bit k: element k is nonzero) and its first two
-// nonzero values, in rank order, in its own 16-byte slot; a thread with more
-// nonzeros stores its E values densely in xdense (B4) and the word
-// kDenseWord.  No thread reads another's data, so the pass needs no
-// workgroup-wide step, and the word and the slot go in flight with Z.
+// column tile owns E elements of X (b + T k, k < E, of its column).  A
+// thread with nonzeros keeps a 32-byte record (its support word, bit k:
+// element k is nonzero, and its first two nonzero values in rank order); a
+// thread with more than two stores its E values densely in xdense (B4) and
+// the word kDenseWord in its record; a thread without nonzeros stores
+// nothing.  Per wave, a 64-bit mask of the lanes that hold a record (one
+// 8-byte word, stored by lane 0).  The pass reads the wave mask first, then
+// Z, then the records of the flagged lanes only: buffer accesses past the
+// end of the buffer are dropped without a memory access, so the lanes
+// without a record take an address past the end, and no branch is needed.
+// No thread reads another's record, so the pass needs no workgroup-wide
+// step.
 //   V = F_eta^-1[Z] mu / N_a + X  ->  X+ = S_sigma(V)  ->  X+ (sparse) and
 //   F_eta X+ into out (B4, in place over Z: the next row pass of G reads
 //   it), or X+ row-major (flag 2: the last iteration; flag 1: X = 0).
-// Bytes per pixel: Z read and F_eta X+ written (16), the word read and
-// written (8/E), the slot read (16/E) and written where nonzero.
-constexpr uint32_t kDenseWord = 0xFFFFFFFFu;  // (no sparse word has more than two bits)
+// Bytes per pixel: Z read and F_eta X+ written (16), 8 bytes per wave each
+// way, and 32 bytes per thread with nonzeros each way.
+constexpr uint32_t kDenseWord = 0xFFFFFFFFu;  // (a sparse record has at most two bits)
+// A buffer offset past the end of the record and mask buffers (at most
+// 2 bytes per pixel: 134 MB at 8192 x 8192), with room for the 16-byte
+// offsets added to it.
+constexpr uint32_t kPastEnd = 0xF0000000u;
 
 // PIPE: Z of this tile was loaded into pre during the previous tile, and Z
 // of the next tile (next >= 0) is loaded into pre during this one.
@@ -817,7 +826,7 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
                                                   const float2* twl, const TwPowers& hp,
                                                   float2 (&pre)[P::E], int next) {
   constexpr int HSC = HT ? hoisted_pass<P>() : -1;
-  constexpr int N = P::N, E = P::E, T = P::T, C = P::C, CT = P::CT;
+  constexpr int N = P::N, E = P::E, T = P::T, C = P::C, CT = P::CT, W = CT / 64;
   static_assert(E <= 32, "support word holds E bits");
   const uint32_t rmb = clamp_bytes((size_t)N * a.nr * 8), b4b = clamp_bytes(b4_bytes(N, a.nr));
   const bool first = a.flags & 1, last = a.flags & 2;
@@ -825,22 +834,33 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
   const Addr ab = col_addr(B4, b, j, T, a.nr);
   const Buf zin(a.in1, b4b), xd(a.xdense, b4b);
   const uint32_t ntiles = (uint32_t)(a.nr / C);
-  const Buf slots(a.xslots, clamp_bytes((size_t)ntiles * CT * 16));
-  const uint32_t word = (uint32_t)tile * CT + threadIdx.x;
-  // the iterate's support word and slot, then Z
-  uint32_t m_old = 0;
-  float4 s01 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const Buf recs(a.xrec, clamp_bytes((size_t)ntiles * CT * 32));
+  const Buf wmasks(a.xwmask, clamp_bytes((size_t)ntiles * W * 8));
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t rec_off = ((uint32_t)tile * CT + threadIdx.x) * 32u;
+  const uint32_t wm_off = ((uint32_t)tile * W + wid) * 8u;
+  // the wave's mask, then Z, then the records of the flagged lanes
+  uint32_t wm_lo = 0, wm_hi = 0;
   if (!first) {
-    m_old = a.xsupp[word];
-    s01 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots.r, word * 16u, 0, 0));
+    const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(wmasks.r, wm_off, 0, 0);
+    wm_lo = w2[0];
+    wm_hi = w2[1];
   }
   const float ms = a.mu * a.scale;
   float2 v[E];
 #pragma unroll
-  for (int k = 0; k < E; ++k) v[k] = cscale(PIPE ? pre[k] : zin.f2(ab.voff, k * ab.kstep), ms);
+  for (int k = 0; k < E; ++k) v[k] = PIPE ? pre[k] : zin.f2(ab.voff, k * ab.kstep);
   if constexpr (PIPE) {
     if (next >= 0) col_preload<P, COL_AS>(a, next, b, c, pre);
   }
+  __builtin_amdgcn_sched_barrier(0);
+  const bool has = ((lane < 32 ? wm_lo >> lane : wm_hi >> (lane - 32)) & 1u) != 0u;
+  const uint32_t ro = has ? rec_off : kPastEnd;
+  const float4 r0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(recs.r, ro, 0, 0));
+  const float4 r1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(recs.r, ro + 16u, 0, 0));
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < E; ++k) v[k] = cscale(v[k], ms);
   const TwLds tws{twl, twl + 64};
   int lb = b, lc = c;
   asm volatile("" : "+v"(lb), "+v"(lc));  // recompute LDS addresses per tile
@@ -848,16 +868,17 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
   // V = ... + X.  Nonzeros are rare, so each element's addition and capture
   // below run only where some lane of the wave needs them (a wave-uniform
   // branch on the ballot), not as selects in every lane.
+  const uint32_t m_old = __float_as_uint(r0.x);  // (0 for a lane without a record)
   if (m_old == kDenseWord) {
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = cadd(v[k], xd.f2(ab.voff, k * ab.kstep));
   } else {
-    const uint32_t k0 = m_old & (0u - m_old);  // lowest set bit: the first slot
+    const uint32_t k0 = m_old & (0u - m_old);  // lowest set bit: the first value
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const bool bit = (m_old >> k) & 1u;
       if (__ballot(bit)) {
-        const float2 x = (k0 >> k) & 1u ? make_float2(s01.x, s01.y) : make_float2(s01.z, s01.w);
+        const float2 x = (k0 >> k) & 1u ? make_float2(r0.y, r0.z) : make_float2(r1.x, r1.y);
         if (bit) v[k] = cadd(v[k], x);
       }
     }
@@ -866,7 +887,7 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
   // the support and the first two nonzeros as they come
   const float s2 = a.sigma * a.sigma;
   uint32_t m_new = 0;
-  float4 x01 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float2 x0 = make_float2(0.f, 0.f), x1 = x0;
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const float m2 = fmaf(v[k].x, v[k].x, v[k].y * v[k].y);
@@ -875,13 +896,8 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
     v[k] = cscale(v[k], f);
     if (__ballot(keep)) {
       if (keep) {
-        if (m_new == 0u) {
-          x01.x = v[k].x;
-          x01.y = v[k].y;
-        } else {
-          x01.z = v[k].x;
-          x01.w = v[k].y;
-        }
+        if (m_new == 0u) x0 = v[k];
+        else x1 = v[k];
         m_new |= 1u << k;
       }
     }
@@ -893,17 +909,27 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
     for (int k = 0; k < E; ++k) out.st(v[k], ar.voff, k * ar.kstep);
     return;
   }
-  if (__builtin_popcount(m_new) <= 2) {
-    a.xsupp[word] = m_new;
-    if (m_new) {
-      using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(slots.r, 0u, 0u, 0));
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, x01), slots.r, word * 16u, 0, 0);
-    }
-  } else {
-    a.xsupp[word] = kDenseWord;
+  // the record (or the dense store) and the wave's mask
+  const bool dense = __builtin_popcount(m_new) > 2;
+  const uint32_t word = dense ? kDenseWord : m_new;
+  const uint32_t wo = m_new ? rec_off : kPastEnd;
+  using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(recs.r, 0u, 0u, 0));
+  __builtin_amdgcn_raw_buffer_store_b128(
+      __builtin_bit_cast(V4, make_float4(__uint_as_float(word), x0.x, x0.y, 0.f)), recs.r, wo, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, make_float4(x1.x, x1.y, 0.f, 0.f)), recs.r,
+                                         wo + 16u, 0, 0);
+  if (__ballot(dense)) {
+    if (dense) {
 #pragma unroll
-    for (int k = 0; k < E; ++k) xd.st(v[k], ab.voff, k * ab.kstep);
+      for (int k = 0; k < E; ++k) xd.st(v[k], ab.voff, k * ab.kstep);
+    }
   }
+  const unsigned long long nz = __ballot(m_new != 0u);
+  using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(wmasks.r, 0u, 0u, 0));
+  V2 wv;
+  wv[0] = (uint32_t)nz;
+  wv[1] = (uint32_t)(nz >> 32);
+  __builtin_amdgcn_raw_buffer_store_b64(wv, wmasks.r, lane == 0 ? wm_off : kPastEnd, 0, 0);
   asm volatile("" : "+v"(lb), "+v"(lc));
   fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);  // F_eta X+
   const Buf out(a.out, b4b);
