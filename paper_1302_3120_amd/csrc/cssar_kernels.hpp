@@ -874,32 +874,37 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
     for (int k = 0; k < E; ++k) v[k] = cadd(v[k], xd.f2(ab.voff, k * ab.kstep));
   } else {
     const uint32_t k0 = m_old & (0u - m_old);  // lowest set bit: the first value
+    if (__ballot(m_old != 0u)) {
 #pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const bool bit = (m_old >> k) & 1u;
-      if (__ballot(bit)) {
+      for (int k = 0; k < E; ++k) {
+        const bool bit = (m_old >> k) & 1u;
         const float2 x = (k0 >> k) & 1u ? make_float2(r0.y, r0.z) : make_float2(r1.x, r1.y);
-        if (bit) v[k] = cadd(v[k], x);
+        v[k] = cadd(v[k], bit ? x : make_float2(0.f, 0.f));
       }
     }
   }
   // X+ = S_sigma(V) (the arithmetic of the azimuth-spectrum update pass);
   // the support and the first two nonzeros as they come
+  // (the threshold in one branch-free block, so the reciprocal square roots
+  // of all elements are in flight together; the capture after it)
   const float s2 = a.sigma * a.sigma;
   uint32_t m_new = 0;
-  float2 x0 = make_float2(0.f, 0.f), x1 = x0;
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const float m2 = fmaf(v[k].x, v[k].x, v[k].y * v[k].y);
     const bool keep = m2 > s2;
     const float f = keep ? fmaf(-a.sigma, rsqrtf(m2), 1.0f) : 0.0f;
     v[k] = cscale(v[k], f);
-    if (__ballot(keep)) {
-      if (keep) {
-        if (m_new == 0u) x0 = v[k];
-        else x1 = v[k];
-        m_new |= 1u << k;
-      }
+    m_new |= keep ? 1u << k : 0u;
+  }
+  float2 x0 = make_float2(0.f, 0.f), x1 = x0;
+  const uint32_t n0 = m_new & (0u - m_new);  // lowest set bit: the first value
+  const uint32_t n1 = (m_new ^ n0) & (0u - (m_new ^ n0));  // the second
+  if (__ballot(m_new != 0u)) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      x0 = (n0 >> k) & 1u ? v[k] : x0;
+      x1 = (n1 >> k) & 1u ? v[k] : x1;
     }
   }
   if (last) {
