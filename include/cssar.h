@@ -238,8 +238,9 @@ int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bi
  * autotuner picks, per line length and pass kind, the kernel plan variant
  * and the number of resident workgroups per compute unit by measuring them.
  * Results equal those of cssar_ita_solve on each scene (bit for bit with
- * the default plans, within rounding with tuned plans); residual norms and
- * the non-finite check are not formed. */
+ * the default plans, within rounding with tuned plans).  Residual norms are
+ * not formed; each call checks every X^(iters) for NaN or Inf instead
+ * (cssar_batch_sync_status). */
 typedef struct cssar_batch cssar_batch;
 
 /* Group count >= 1 operators (all made on the current device).  The
@@ -261,15 +262,21 @@ int cssar_batch_set_graph(cssar_batch* b, int on);
 
 /* Measure the plan variants and workgroups-per-CU choices of the row pass
  * and of the residual and update column passes for every line length of the
- * batch, and graph versus direct launches; keep the fastest.  ws: a batch
+ * batch, and graph versus direct launches; keep the fastest.  Before any
+ * timing, every plan variant runs the pass on a seeded input beside the
+ * default plan (the single-array solver's): a variant whose output lies
+ * more than 1e-5 (relative L2 over the group's scenes) from the default's
+ * is never chosen, also when the cache names it; cssar_batch_describe
+ * reports each distance.  ws: a batch
  * workspace (cssar_batch_workspace_size bytes; clobbered).  cache_path:
  * NULL, or a text file of earlier results (one line per choice, keyed by the
  * device, pass, length and amount of work); matching lines are used without
  * measuring and new results are appended.  Synchronises the stream. */
 int cssar_batch_autotune(cssar_batch* b, void* ws, const char* cache_path, void* stream);
 
-/* Current choices as text (one line per pass kind and length, then the
- * launch mode) into buf (NUL-terminated, truncated to len).  Returns the
+/* Current choices as text (one line per pass kind and length, with the
+ * parity-gate distance of every plan variant, "-" where not measured; then
+ * the launch mode) into buf (NUL-terminated, truncated to len).  Returns the
  * full length. */
 int cssar_batch_describe(const cssar_batch* b, char* buf, int len);
 
@@ -281,6 +288,11 @@ int cssar_batch_describe(const cssar_batch* b, char* buf, int len);
 int cssar_ita_solve_batched(cssar_batch* b, const void* const* ys, const void* const* mask_bits,
                             const float* lambdas, int iters, void* const* x_outs, void* ws,
                             void* stream);
+
+/* Wait for the stream; if a call since the last check left NaN or Inf in
+ * some scene's X^(iters), return CSSAR_ENONFINITE with *scene (if not NULL)
+ * the first such scene (else -1), and clear the flags. */
+int cssar_batch_sync_status(cssar_batch* b, void* stream, int* scene);
 
 /* ------------------------------------------------------------- gradient --
  * Derivatives of a loss L(X^(K)) of K unrolled iterations of eq. (th2d) /

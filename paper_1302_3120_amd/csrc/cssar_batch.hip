@@ -45,7 +45,19 @@ struct Group {
   std::vector<int> scenes;  // indices into the batch
   Choice ch[TK_COUNT];
   Slot slot[SL_COUNT];
+  int def_variant[TK_COUNT] = {};  // the single-array solver's plan (the autotuner's reference)
+  // autotuner parity gate: relative L2 distance of each plan variant's output
+  // from the reference plan's on a seeded input (-1: not measured)
+  double gate[TK_COUNT][kMaxVariants];
+  Group() {
+    for (auto& r : gate)
+      for (double& e : r) e = -1.0;
+  }
 };
+
+// A plan variant is accepted by the autotuner only within this distance of
+// the reference plan's output (relative L2 over the group's scenes).
+constexpr double kGateTol = 1e-5;
 
 bool slot_used(const Group& g, int k) {
   return g.row ? (k == SL_ROW_M || k == SL_ROW_G) : (k >= SL_FWD);
@@ -85,6 +97,79 @@ hipError_t launch_col_group(const KernelTable* kt, int ck, const GroupArgs& g, i
   return ck == CK_AS ? kt->col_group_as(g, grid, s) : kt->col_group[ck](g, grid, s);
 }
 
+// ------------------------------------------------ seeded fill and distance --
+// 32-bit integer hash (the "lowbias32" mix of shifts and odd multipliers
+// published by C. Wellons' hash-prospector project).
+__device__ inline uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// n complex values, each part uniform in [-1, 1), from the hash of (seed,
+// index): the autotuner's test input.
+__global__ __launch_bounds__(256) void gate_fill_kernel(float2* __restrict__ p, size_t n, uint32_t seed) {
+  const size_t step = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+    const uint32_t h = mix32(seed * 0x9e3779b9u ^ (uint32_t)(i >> 32) * 0x85ebca6bu);
+    const uint32_t a = mix32(h ^ (uint32_t)(2 * i)), b = mix32(h ^ (uint32_t)(2 * i + 1));
+    p[i] = make_float2((float)(a >> 8) * (1.0f / 8388608.0f) - 1.0f, (float)(b >> 8) * (1.0f / 8388608.0f) - 1.0f);
+  }
+}
+
+constexpr int kGateBlocks = 256;
+
+// Per block: sum |a - r|^2 and sum |r|^2 (FP64) into part[2 blk], part[2 blk + 1].
+__global__ __launch_bounds__(256) void gate_diff_kernel(const float2* __restrict__ a, const float2* __restrict__ r,
+                                                        size_t n, double* __restrict__ part) {
+  __shared__ double sd[256], sr[256];
+  double d = 0.0, q = 0.0;
+  const size_t step = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+    const float2 x = a[i], y = r[i];
+    const double dx = (double)x.x - y.x, dy = (double)x.y - y.y;
+    d += dx * dx + dy * dy;
+    q += (double)y.x * y.x + (double)y.y * y.y;
+  }
+  sd[threadIdx.x] = d;
+  sr[threadIdx.x] = q;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sd[threadIdx.x] += sd[threadIdx.x + w];
+      sr[threadIdx.x] += sr[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sd[0];
+    part[2 * blockIdx.x + 1] = sr[0];
+  }
+}
+
+// ---------------------------------------------------------- finite check --
+struct CheckArg {
+  const float4* x;  // X of the scene (two complex values per float4)
+  long long n4;     // float4 count
+};
+
+// Bit 0 of status[scene] when X of the scene (blockIdx.y) holds a NaN or an
+// infinity.
+__global__ __launch_bounds__(256) void finite_check_kernel(const CheckArg* __restrict__ args,
+                                                           unsigned* __restrict__ status) {
+  const CheckArg a = args[blockIdx.y];
+  bool bad = false;
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < a.n4; i += step) {
+    const float4 v = a.x[i];
+    bad |= !(isfinite(v.x) && isfinite(v.y) && isfinite(v.z) && isfinite(v.w));
+  }
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(status + blockIdx.y, 1u);
+}
+
 }  // namespace
 
 struct cssar_batch {
@@ -97,6 +182,9 @@ struct cssar_batch {
   std::vector<Group> groups;
   size_t table_bytes = 0;
   char* dev_table = nullptr;   // device copy of the argument tables
+  size_t check_off = 0;        // byte offset of the finite-check arguments in the table block
+  unsigned* status = nullptr;  // per scene: bit 0 non-finite X (finite_check_kernel)
+  double* gate_part = nullptr; // per-block sums of gate_diff_kernel
   char* staging = nullptr;     // pinned host staging of the same
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
@@ -218,6 +306,12 @@ int upload_tables(cssar_batch* b, const CallArgs& c, hipStream_t s) {
       start[g.scenes.size()] = acc;
     }
   }
+  CheckArg* ck = (CheckArg*)(h + b->check_off);
+  for (size_t si = 0; si < b->ops.size(); ++si) {
+    const cssar_op* op = b->ops[si];
+    ck[si].x = c.x_outs ? (const float4*)c.x_outs[si] : nullptr;
+    ck[si].n4 = c.x_outs ? (long long)op->na * op->nr / 2 : 0;
+  }
   HIP_TRY(hipMemcpyAsync(b->dev_table, b->staging, b->table_bytes, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(b->upload_done, s));
   b->upload_pending = true;
@@ -309,6 +403,95 @@ std::string graph_key(const cssar_batch* b) {
   return o.str();
 }
 
+// --------------------------------------------------------- parity gate --
+// Runs the pass of tune kind tk of group g with its current choice on a
+// seeded input, leaving the output in every scene's P.  The update pass runs
+// twice (first, then middle iteration, on two inputs), so the second reads
+// the sparse iterate the first wrote; its threshold keeps about 5 % of the
+// values (the inverse FFT of values uniform in [-1, 1) per part, scaled by
+// 1/N_a, has per-part variance 1/(3 N_a); sigma^2 = 2/N_a keeps exp(-3)).
+int gate_run(cssar_batch* b, Group& g, int tk, const CallArgs& c, hipStream_t s) {
+  plan_slots(b);
+  int rc = upload_tables(b, c, s);
+  if (rc) return rc;
+  auto fill = [&](char* p, size_t bytes, uint32_t seed) {
+    hipLaunchKernelGGL(gate_fill_kernel, dim3(512), dim3(256), 0, s, (float2*)p, bytes / sizeof(float2), seed);
+    return hipGetLastError();
+  };
+  for (int si : g.scenes) {
+    char* base = c.ws + b->ws_off[si];
+    const size_t blk = b->blk[si];
+    HIP_TRY(fill(base + blk, blk, 1u));
+    if (tk == TK_R) HIP_TRY(fill(base + 2 * blk, blk, 2u));
+    if (tk == TK_A) {
+      HIP_TRY(hipMemsetAsync(base, 0, blk, s));
+      HIP_TRY(hipMemsetAsync(base + 3 * blk, 0, sparse_bytes_max(b->ops[si]), s));
+    }
+  }
+  if (tk == TK_ROW) return launch_slot(b, g, SL_ROW_M, s);
+  if (tk == TK_R) return launch_slot(b, g, SL_R, s);
+  if ((rc = launch_slot(b, g, SL_A_FIRST, s))) return rc;
+  for (int si : g.scenes) HIP_TRY(fill(c.ws + b->ws_off[si] + b->blk[si], b->blk[si], 3u));
+  return launch_slot(b, g, SL_A_MID, s);
+}
+
+// The gate of every plan variant of (g, tk) that fits: relative L2 distance
+// of its output from the reference plan's (g.def_variant) over the group's
+// scenes, into g.gate[tk].  The reference output is kept in a blocked array
+// of each scene that the pass does not use (Y; X's dense tiles for the
+// residual pass, which reads Y).  Leaves the workspace clobbered.
+int gate_variants(cssar_batch* b, Group& g, int tk, char* ws, hipStream_t s) {
+  const Choice keep = g.ch[tk];
+  std::vector<float> lam(b->ops.size());
+  for (size_t i = 0; i < lam.size(); ++i) lam[i] = std::sqrt(2.0f / (float)b->ops[i]->na);
+  CallArgs c;
+  c.ws = ws;
+  c.lambdas = lam.data();
+  const size_t ref_at = tk == TK_R ? 0 : 2;  // in blocked arrays from the scene's base
+  auto restore = [&](int rc) {
+    g.ch[tk] = keep;
+    plan_slots(b);
+    return rc;
+  };
+  g.ch[tk] = Choice{g.def_variant[tk], 0};
+  int rc = gate_run(b, g, tk, c, s);
+  if (rc) return restore(rc);
+  for (int si : g.scenes) {
+    char* base = ws + b->ws_off[si];
+    if (hipMemcpyAsync(base + ref_at * b->blk[si], base + b->blk[si], b->blk[si], hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+      return restore(fail(CSSAR_EHIP, "hipMemcpyAsync failed"));
+  }
+  g.gate[tk][g.def_variant[tk]] = 0.0;
+  std::vector<double> part(2 * kGateBlocks);
+  for (int v = 0; v < kMaxVariants; ++v) {
+    const KernelTable* kt = table_for(g.n, v);
+    if (v == g.def_variant[tk] || !kt || !variant_fits(b, g, kt)) continue;
+    g.ch[tk] = Choice{v, 0};
+    if ((rc = gate_run(b, g, tk, c, s))) return restore(rc);
+    double d = 0.0, r = 0.0;
+    for (int si : g.scenes) {
+      const char* base = ws + b->ws_off[si];
+      hipLaunchKernelGGL(gate_diff_kernel, dim3(kGateBlocks), dim3(256), 0, s,
+                         (const float2*)(base + b->blk[si]), (const float2*)(base + ref_at * b->blk[si]),
+                         b->blk[si] / sizeof(float2), b->gate_part);
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(part.data(), b->gate_part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return restore(fail(CSSAR_EHIP, "parity gate: distance kernel failed"));
+      for (int k = 0; k < kGateBlocks; ++k) {
+        d += part[2 * k];
+        r += part[2 * k + 1];
+      }
+    }
+    // a non-finite distance fails the gate (stored as +inf)
+    const double e = r > 0.0 ? std::sqrt(d / r) : (d > 0.0 ? HUGE_VAL : 0.0);
+    g.gate[tk][v] = std::isfinite(e) ? e : HUGE_VAL;
+  }
+  return restore(CSSAR_OK);
+}
+
 // Time `reps` launches of fn (after one warm-up), in microseconds each.
 template <typename F>
 int time_launches(hipStream_t s, int reps, F&& fn, double* us) {
@@ -396,12 +579,16 @@ int cssar_make_batch(cssar_op* const* ops, int count, cssar_batch** out) {
     if (g.row) {
       const KernelTable* kt = table_for(g.n, row_variant(g.n));
       if (kt && variant_fits(b, g, kt)) g.ch[TK_ROW].variant = row_variant(g.n);
-      continue;
+    } else {
+      for (int tk : {(int)TK_R, (int)TK_A}) {
+        const int v = column_variant(g.n, tk == TK_R ? CK_R : CK_AS);
+        const KernelTable* kt = table_for(g.n, v);
+        if (kt && variant_fits(b, g, kt)) g.ch[tk].variant = v;
+      }
     }
-    for (int tk : {(int)TK_R, (int)TK_A}) {
-      const int v = column_variant(g.n, tk == TK_R ? CK_R : CK_AS);
-      const KernelTable* kt = table_for(g.n, v);
-      if (kt && variant_fits(b, g, kt)) g.ch[tk].variant = v;
+    for (int tk = 0; tk < TK_COUNT; ++tk) {
+      g.def_variant[tk] = g.ch[tk].variant;
+      g.gate[tk][g.ch[tk].variant] = 0.0;
     }
   }
   // table block layout: per used slot, the argument array and the prefix sums
@@ -416,8 +603,15 @@ int cssar_make_batch(cssar_op* const* ops, int count, cssar_batch** out) {
       tb = align256(tb + sizeof(int) * (g.scenes.size() + 1));
     }
   }
+  b->check_off = tb;
+  tb = align256(tb + sizeof(CheckArg) * count);
   b->table_bytes = tb;
   if (hipMalloc(&b->dev_table, tb) != hipSuccess) return cleanup(fail(CSSAR_ENOMEM, "hipMalloc of %zu bytes failed", tb));
+  if (hipMalloc(&b->status, sizeof(unsigned) * count) != hipSuccess ||
+      hipMalloc(&b->gate_part, sizeof(double) * 2 * kGateBlocks) != hipSuccess)
+    return cleanup(fail(CSSAR_ENOMEM, "hipMalloc of the status words failed"));
+  if (hipMemset(b->status, 0, sizeof(unsigned) * count) != hipSuccess)
+    return cleanup(fail(CSSAR_EHIP, "hipMemset failed"));
   if (hipHostMalloc(&b->staging, tb, hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(CSSAR_ENOMEM, "hipHostMalloc of %zu bytes failed", tb));
   std::memset(b->staging, 0, tb);
@@ -435,6 +629,8 @@ int cssar_destroy_batch(cssar_batch* b) {
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
   if (b->upload_done) (void)hipEventDestroy(b->upload_done);
   if (b->dev_table) (void)hipFree(b->dev_table);
+  if (b->status) (void)hipFree(b->status);
+  if (b->gate_part) (void)hipFree(b->gate_part);
   if (b->staging) (void)hipHostFree(b->staging);
   delete b;
   return CSSAR_OK;
@@ -457,7 +653,17 @@ int cssar_batch_describe(const cssar_batch* b, char* buf, int len) {
       const Slot& sl = g.slot[tk == TK_ROW ? SL_ROW_M : (tk == TK_R ? SL_R : SL_A_MID)];
       o << kTuneName[tk] << " n=" << g.n << " scenes=" << g.scenes.size() << " variant=" << g.ch[tk].variant
         << " E=" << sl.kt->E << " " << (g.row ? "rows/wg=" : "cols/wg=") << (g.row ? sl.kt->LR : sl.kt->C)
-        << " per_cu=" << g.ch[tk].per_cu << " grid=" << sl.grid << " units=" << sl.total << "\n";
+        << " per_cu=" << g.ch[tk].per_cu << " grid=" << sl.grid << " units=" << sl.total << " gate=";
+      // per plan variant: relative L2 distance from the reference plan's
+      // output ("-": not measured; the reference itself is 0)
+      for (int v = 0; v < kMaxVariants; ++v) {
+        if (!table_for(g.n, v)) continue;
+        char e[32];
+        if (g.gate[tk][v] < 0.0) std::snprintf(e, sizeof e, "%s%d:-", v ? "," : "", v);
+        else std::snprintf(e, sizeof e, "%s%d:%.2e", v ? "," : "", v, g.gate[tk][v]);
+        o << e;
+      }
+      o << "\n";
     }
   }
   o << "graph=" << (b->use_graph ? 1 : 0) << "\n";
@@ -494,7 +700,30 @@ int cssar_ita_solve_batched(cssar_batch* b, const void* const* ys, const void* c
   c.ws = (char*)ws;
   int rc = upload_tables(b, c, s);
   if (rc) return rc;
-  return run_iterations(b, iters, s);
+  if ((rc = run_iterations(b, iters, s))) return rc;
+  // the non-finite check of every X^(iters) (read once per call)
+  hipLaunchKernelGGL(finite_check_kernel, dim3(64, (unsigned)b->ops.size()), dim3(256), 0, s,
+                     (const CheckArg*)(b->dev_table + b->check_off), b->status);
+  HIP_TRY(hipGetLastError());
+  return CSSAR_OK;
+}
+
+int cssar_batch_sync_status(cssar_batch* b, void* stream, int* scene) {
+  if (scene) *scene = -1;
+  if (!b) return fail(CSSAR_EINVAL, "batch is NULL");
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  std::vector<unsigned> st(b->ops.size());
+  HIP_TRY(hipMemcpy(st.data(), b->status, sizeof(unsigned) * st.size(), hipMemcpyDeviceToHost));
+  int first = -1, bad = 0;
+  for (size_t i = 0; i < st.size(); ++i)
+    if (st[i]) {
+      if (first < 0) first = (int)i;
+      ++bad;
+    }
+  if (first < 0) return CSSAR_OK;
+  HIP_TRY(hipMemset(b->status, 0, sizeof(unsigned) * st.size()));
+  if (scene) *scene = first;
+  return fail(CSSAR_ENONFINITE, "non-finite image in %d scene(s), the first is scene %d", bad, first);
 }
 
 int cssar_batch_autotune(cssar_batch* b, void* ws, const char* cache_path, void* stream) {
@@ -512,7 +741,6 @@ int cssar_batch_autotune(cssar_batch* b, void* ws, const char* cache_path, void*
   }
   std::vector<std::string> fresh;
   drop_graph(b);
-  HIP_TRY(hipMemsetAsync(ws, 0, b->ws_bytes, s));
   CallArgs c;
   c.ws = (char*)ws;
   const int reps = 3;
@@ -520,12 +748,20 @@ int cssar_batch_autotune(cssar_batch* b, void* ws, const char* cache_path, void*
     for (int tk = 0; tk < TK_COUNT; ++tk) {
       if (g.row != (tk == TK_ROW)) continue;
       const int slot = tk == TK_ROW ? SL_ROW_M : (tk == TK_R ? SL_R : SL_A_MID);
+      // every variant is checked against the reference plan first (also
+      // when the choice comes from the cache); one outside the gate is
+      // never taken
+      int rc = gate_variants(b, g, tk, (char*)ws, s);
+      if (rc) return rc;
+      auto gated = [&](int v) { return g.gate[tk][v] >= 0.0 && g.gate[tk][v] <= kGateTol; };
+      // timing runs on a zeroed workspace (an empty iterate)
+      HIP_TRY(hipMemsetAsync(ws, 0, b->ws_bytes, s));
       const std::string key = tune_key(b, g, tk);
       auto it = cache.find(key);
       if (it != cache.end()) {
         int v = 0, pc = 0;
-        if (std::sscanf(it->second.c_str(), "%d %d", &v, &pc) == 2 && table_for(g.n, v) &&
-            variant_fits(b, g, table_for(g.n, v))) {
+        if (std::sscanf(it->second.c_str(), "%d %d", &v, &pc) == 2 && v >= 0 && v < kMaxVariants &&
+            table_for(g.n, v) && variant_fits(b, g, table_for(g.n, v)) && gated(v)) {
           g.ch[tk].variant = v;
           g.ch[tk].per_cu = pc;
           continue;
@@ -533,16 +769,17 @@ int cssar_batch_autotune(cssar_batch* b, void* ws, const char* cache_path, void*
       }
       double best = 1e30;
       Choice bestc;
+      bestc.variant = g.def_variant[tk];
       for (int v = 0; v < kMaxVariants; ++v) {
         const KernelTable* kt = table_for(g.n, v);
-        if (!kt || !variant_fits(b, g, kt)) continue;
+        if (!kt || !variant_fits(b, g, kt) || !gated(v)) continue;
         const void* fn = g.row ? kt->row_group_fn : col_group_fn(kt, col_mode(slot));
         const int occ = occupancy(fn, g.row ? kt->RT : kt->CT);
         for (int pc = 1; pc <= occ; ++pc) {
           g.ch[tk].variant = v;
           g.ch[tk].per_cu = pc;
           plan_slots(b);
-          int rc = upload_tables(b, c, s);
+          rc = upload_tables(b, c, s);
           if (rc) return rc;
           double us = 0;
           rc = time_launches(s, reps, [&] { return launch_slot(b, g, slot, s); }, &us);

@@ -29,7 +29,7 @@ SYMBOLS = (
     "cssar_ita_solve_batched", "cssar_checkpoint_size", "cssar_grad_workspace_size",
     "cssar_ita_forward", "cssar_ita_backward", "cssar_ita_solve_adaptive",
     "cssar_make_operator_rda", "cssar_operator_chain", "cssar_ita_solve_safeguarded",
-    "cssar_azimuth_fm_rate", "cssar_params_with_rates",
+    "cssar_azimuth_fm_rate", "cssar_params_with_rates", "cssar_batch_sync_status",
 )
 
 PROFILE_KINDS = ("row_M", "row_G", "col_fwd", "col_inv", "col_update_threshold",
@@ -107,6 +107,7 @@ def lib():
         L.cssar_batch_autotune.argtypes = [vp, vp, ctypes.c_char_p, vp]
         L.cssar_batch_describe.argtypes = [vp, ctypes.c_char_p, i]
         L.cssar_ita_solve_batched.argtypes = [vp, pp, pp, ctypes.POINTER(f), i, pp, vp, vp]
+        L.cssar_batch_sync_status.argtypes = [vp, vp, ctypes.POINTER(i)]
         L.cssar_checkpoint_size.argtypes = [vp, i, i]
         L.cssar_checkpoint_size.restype = ctypes.c_size_t
         L.cssar_grad_workspace_size.argtypes = [vp, i]
@@ -125,7 +126,7 @@ def lib():
                      "cssar_sync_status", "cssar_supported_length", "cssar_plan_info",
                      "cssar_profile_enable", "cssar_profile_read", "cssar_make_batch",
                      "cssar_destroy_batch", "cssar_batch_set_graph", "cssar_batch_autotune",
-                     "cssar_batch_describe", "cssar_ita_solve_batched"):
+                     "cssar_batch_describe", "cssar_ita_solve_batched", "cssar_batch_sync_status"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -397,6 +398,12 @@ class Batch:
         buf = ctypes.create_string_buffer(max(n, 0) + 1)
         lib().cssar_batch_describe(self._h, buf, len(buf))
         return buf.value.decode()
+
+    def sync_status(self):
+        """Wait for the stream; raise CssarError (CSSAR_ENONFINITE, naming the
+        first scene) if a call left NaN or Inf in some X^(iters)."""
+        sc = ctypes.c_int(-1)
+        _check(lib().cssar_batch_sync_status(self._h, _stream(), ctypes.byref(sc)))
 
     def ita_solve(self, ys, mask_bits, lams, iters, outs=None, ws=None):
         """Iterative thresholding of every scene; returns the list of X^(iters)."""

@@ -56,6 +56,20 @@ def _random_batch(shapes, seed, dev):
     return ops, ys, masks, bits, lams
 
 
+def _check_gate(desc):
+    """Every plan variant of every tuned pass was run through the parity
+    gate (a distance, not "-"), and the chosen one is within 1e-5 of the
+    default plan's output."""
+    lines = [l for l in desc.splitlines() if " gate=" in l]
+    assert lines
+    for l in lines:
+        chosen = int(l.split(" variant=")[1].split()[0])
+        gates = dict(g.split(":") for g in l.split(" gate=")[1].split(","))
+        assert all(v != "-" for v in gates.values()), l
+        assert float(gates[str(chosen)]) <= 1e-5, l
+        say(f"    gate {l.split(' scenes=')[0]}: {gates}")
+
+
 # (2048 and 4096 columns run plan variant 1 for the update / residual pass by default)
 SMALL = [(256, 512), (512, 256), (768, 1024), (1024, 768), (512, 512), (256, 256), (1536, 512),
          (2048, 256), (4096, 64)]
@@ -111,6 +125,7 @@ def test_autotuned_batch_matches_oracle(dev, tmp_path):
     cache = str(tmp_path / "tune.txt")
     b.autotune(cache_path=cache)
     say("    " + b.describe().replace("\n", "; "))
+    _check_gate(b.describe())
     ys = [_d(p[1], dev) for p in probs]
     bits = [op.pack_mask(torch.from_numpy(p[2]).to(dev)) for op, p in zip(ops, probs)]
     lams = [p[3] for p in probs]
@@ -144,7 +159,9 @@ def test_batched_64_scene_workload(dev):
     b = pk.make_batch(ops)
     b.autotune()
     say("    " + b.describe().replace("\n", "; "))
+    _check_gate(b.describe())
     outs = b.ita_solve(ys, bits, lams, wl["iters"])
+    b.sync_status()
     worst = 0.0
     for s, op in enumerate(ops):
         ref = op.ita_solve(ys[s], bits[s], lams[s], wl["iters"])
@@ -179,3 +196,32 @@ def test_batch_rejects_bad_arguments(dev):
         b.ita_solve(ys, bits, [0.1, 0.1], 3, outs=ys)
     out = b.ita_solve(ys, bits, [0.1, 0.1], 3)
     assert all(float(o.abs().max()) == 0.0 for o in out)
+
+
+def test_batched_nonfinite_scene_is_reported(dev):
+    # A NaN at a sampled entry of one scene's y spreads through that scene's
+    # iteration; the call's check of every X^(iters) reports that scene (the
+    # others stay finite and equal their per-scene solves), and the flag is
+    # cleared by the report.  A NaN outside the mask is ignored.
+    import paper_1302_3120_amd as pk
+    shapes = [(256, 256), (512, 256), (256, 512)]
+    say(f"[gpu] batched non-finite check {shapes}")
+    ops, ys, masks, bits, lams = _random_batch(shapes, 21, dev)
+    b = pk.make_batch(ops)
+    bad = ys[1].clone()
+    i, j = (int(t) for t in torch.nonzero(masks[1])[5])
+    bad[i, j] = float("nan")
+    outs = b.ita_solve([ys[0], bad, ys[2]], bits, lams, 4)
+    with pytest.raises(pk.CssarError) as e:
+        b.sync_status()
+    assert e.value.code == pk.cssar.ENONFINITE and "scene 1" in str(e.value)
+    for s in (0, 2):
+        assert torch.equal(outs[s], ops[s].ita_solve(ys[s], bits[s], lams[s], 4))
+    b.sync_status()  # cleared
+    # NaN outside the mask: not read
+    un = ys[2].clone()
+    i, j = (int(t) for t in torch.nonzero(~masks[2])[3])
+    un[i, j] = float("nan")
+    outs = b.ita_solve([ys[0], ys[1], un], bits, lams, 4)
+    b.sync_status()
+    assert torch.equal(outs[2], ops[2].ita_solve(ys[2], bits[2], lams[2], 4))

@@ -227,6 +227,34 @@ def test_nonfinite_input_is_reported(dev):
     op.sync_status()  # cleared
 
 
+def test_nonfinite_outside_the_mask_is_ignored(dev):
+    # Only m o y enters the method (eq. (th2d)): NaN and Inf at unsampled
+    # entries are not read, on the GPU as in the oracle.  The image equals
+    # the one with zeros there, bit for bit, matches the oracle's, and no
+    # non-finite status is raised.
+    shape = (256, 512)
+    say(f"[gpu] non-finite values outside the mask {shape}")
+    op = _op(shape)
+    mask = inputs.random_mask(shape, 0.4, seed=5)
+    y = np.where(mask, inputs.random_complex(shape, seed=4), 0)
+    un = np.argwhere(~mask)
+    yb = y.copy()
+    yb[tuple(un[7])] = np.nan
+    yb[tuple(un[100])] = np.inf
+    yb[tuple(un[200])] = complex(-np.inf, np.nan)
+    bits = op.pack_mask(torch.from_numpy(mask).to(dev))
+    lam = 0.05
+    xa, ha = op.ita_solve(_d(y, dev), bits, lam, 5, resid=True)
+    xb, hb = op.ita_solve(_d(yb, dev), bits, lam, 5, resid=True)
+    op.sync_status()
+    assert torch.equal(xa, xb) and torch.equal(ha, hb)
+    xo, ho = ita.ita(yb, mask, lam, 5, csa.Geometry(P, shape))
+    e = rel_l2(_h(xb), xo)
+    say(f"    image rel L2 vs oracle {e:.2e}")
+    assert e <= 1e-4
+    np.testing.assert_allclose(hb.cpu().numpy(), ho, rtol=1e-4)
+
+
 def test_wide_swath_8192_sampled_columns(dev):
     # The 8192 x 8192 wide-swath configuration (all state resident): G, G^H
     # and the first ITA iterate on sampled columns the oracle computes one by
