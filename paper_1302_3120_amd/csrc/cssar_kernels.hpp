@@ -161,10 +161,11 @@ struct ColArgs {
   const uint32_t* supp_old;  // T: support bits of the iterate X (compared with X+'s)
   float2* out3;          // T with flag 16: X+ (spatial, row-major)
   const unsigned* gate;  // if not NULL, the pass does nothing while *gate == 0
-  // sparse iterate (AS, col_update_sparse): per column tile, the 32-byte
-  // record of every thread with nonzeros (index tile * CT + thread), the
-  // 64-bit lane mask of every wave (index tile * CT/64 + wave), and the dense
-  // store of the threads with more than two nonzeros
+  // sparse iterate (AS, col_update_sparse): per column tile, an area of 64
+  // 32-byte records per wave (index tile * CT + 64 wave + slot) holding the
+  // records of the wave's threads with nonzeros, packed; the 64-bit lane
+  // mask of every wave (index tile * CT/64 + wave); and the dense store of
+  // the threads with more than two nonzeros
   float4* xrec;
   uint64_t* xwmask;
   float2* xdense;        // B4
@@ -802,12 +803,15 @@ __device__ __forceinline__ MaskAddr mask_addr(int b, int j, int T, int nr) {
 // thread with more than two stores its E values densely in xdense (B4) and
 // the word kDenseWord in its record; a thread without nonzeros stores
 // nothing.  Per wave, a 64-bit mask of the lanes that hold a record (one
-// 8-byte word, stored by lane 0).  The pass reads the wave mask first, then
-// Z, then the records of the flagged lanes only: buffer accesses past the
-// end of the buffer are dropped without a memory access, so the lanes
-// without a record take an address past the end, and no branch is needed.
-// No thread reads another's record, so the pass needs no workgroup-wide
-// step.
+// 8-byte word, stored by lane 0).  A wave's records are packed at the start
+// of its 64-record area, in lane order (a lane's slot is the number of
+// flagged lanes below it), so the few records of a wave share one or two
+// cache lines instead of one line each.  The pass reads the wave mask
+// first, then Z, then the records of the flagged lanes only: buffer
+// accesses past the end of the buffer are dropped without a memory access,
+// so the lanes without a record take an address past the end, and no branch
+// is needed.  No wave reads another's records, so the pass needs no
+// workgroup-wide step.
 //   V = F_eta^-1[Z] mu / N_a + X  ->  X+ = S_sigma(V)  ->  X+ (sparse) and
 //   F_eta X+ into out (B4, in place over Z: the next row pass of G reads
 //   it), or X+ row-major (flag 2: the last iteration; flag 1: X = 0).
@@ -837,7 +841,7 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
   const Buf recs(a.xrec, clamp_bytes((size_t)ntiles * CT * 32));
   const Buf wmasks(a.xwmask, clamp_bytes((size_t)ntiles * W * 8));
   const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint32_t rec_off = ((uint32_t)tile * CT + threadIdx.x) * 32u;
+  const uint32_t wave_rec = ((uint32_t)tile * CT + (threadIdx.x & ~63u)) * 32u;  // the wave's area
   const uint32_t wm_off = ((uint32_t)tile * W + wid) * 8u;
   // the wave's mask, then Z, then the records of the flagged lanes
   uint32_t wm_lo = 0, wm_hi = 0;
@@ -855,7 +859,8 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
   }
   __builtin_amdgcn_sched_barrier(0);
   const bool has = ((lane < 32 ? wm_lo >> lane : wm_hi >> (lane - 32)) & 1u) != 0u;
-  const uint32_t ro = has ? rec_off : kPastEnd;
+  const uint32_t ro = has ? wave_rec + 32u * __builtin_amdgcn_mbcnt_hi(wm_hi, __builtin_amdgcn_mbcnt_lo(wm_lo, 0u))
+                          : kPastEnd;
   const float4 r0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(recs.r, ro, 0, 0));
   const float4 r1 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(recs.r, ro + 16u, 0, 0));
   __builtin_amdgcn_sched_barrier(0);
@@ -917,7 +922,10 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
   // the record (or the dense store) and the wave's mask
   const bool dense = __builtin_popcount(m_new) > 2;
   const uint32_t word = dense ? kDenseWord : m_new;
-  const uint32_t wo = m_new ? rec_off : kPastEnd;
+  const unsigned long long nz = __ballot(m_new != 0u);
+  const uint32_t wo = m_new ? wave_rec + 32u * __builtin_amdgcn_mbcnt_hi((uint32_t)(nz >> 32),
+                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)nz, 0u))
+                            : kPastEnd;
   using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(recs.r, 0u, 0u, 0));
   __builtin_amdgcn_raw_buffer_store_b128(
       __builtin_bit_cast(V4, make_float4(__uint_as_float(word), x0.x, x0.y, 0.f)), recs.r, wo, 0, 0);
@@ -929,7 +937,6 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
       for (int k = 0; k < E; ++k) xd.st(v[k], ab.voff, k * ab.kstep);
     }
   }
-  const unsigned long long nz = __ballot(m_new != 0u);
   using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(wmasks.r, 0u, 0u, 0));
   V2 wv;
   wv[0] = (uint32_t)nz;
