@@ -52,11 +52,13 @@ def soft_threshold(v, sigma):
     return out
 
 
-def ita(y, mask, lam, iters, geom, mu=1.0, x0=None):
+def ita(y, mask, lam, iters, geom, mu=1.0, x0=None, trace=None):
     """Algorithm 1.  Returns (X^(iters), [||R^(0)||^2, ..., ||R^(iters-1)||^2]).
 
     ``y`` is the zero-filled sampled raw data, ``mask`` the sampling mask.
-    ``x0`` (default 0) is the starting iterate.
+    ``x0`` (default 0) is the starting iterate.  ``trace``, if a dict,
+    receives the lists "l1" (||X^(t+1)||_1, the sum of magnitudes) and "nnz"
+    (the nonzero count of X^(t+1)), t = 0 .. iters-1.
     """
     y = np.asarray(y, dtype=np.complex128)
     x = np.zeros_like(y) if x0 is None else np.array(x0, dtype=np.complex128)
@@ -69,6 +71,9 @@ def ita(y, mask, lam, iters, geom, mu=1.0, x0=None):
         hist.append(float(np.vdot(r, r).real))
         dx = _M(r, geom)
         x = soft_threshold(x + mu * dx, lam * mu)
+        if trace is not None:
+            trace.setdefault("l1", []).append(float(np.abs(x).sum()))
+            trace.setdefault("nnz", []).append(int(np.count_nonzero(x)))
     return x, hist
 
 

@@ -162,3 +162,48 @@ def test_entries_outside_the_mask_are_ignored():
     bad = clean.copy()
     bad[tuple(np.argwhere(mask)[0])] = np.nan
     assert not np.all(np.isfinite(ita.ita(bad, mask, 0.05, 1, g)[1]))
+
+
+def test_warm_start_splits_the_iteration():
+    # Algorithm 1 is a fixed-point iteration of X alone: n1 iterations, then
+    # n2 more from X^(n1), are the same arithmetic as n1 + n2 iterations
+    # (bit for bit in the oracle), residual norms included.
+    shape = (32, 64)
+    g = csa.Geometry(P, shape)
+    rng = np.random.default_rng(17)
+    x = np.zeros(shape, dtype=np.complex128)
+    idx = rng.choice(x.size, 40, replace=False)
+    x.flat[idx] = rng.normal(size=40) + 1j * rng.normal(size=40)
+    mask = inputs.random_mask(shape, 0.5, seed=18)
+    y = np.where(mask, csa.G(x, g), 0)
+    lam = 0.05
+    x7, h7 = ita.ita(y, mask, lam, 7, g)
+    x3, h3 = ita.ita(y, mask, lam, 3, g)
+    x34, h34 = ita.ita(y, mask, lam, 4, g, x0=x3)
+    assert np.array_equal(x34, x7) and h3 + h34 == h7
+    # the warm start really starts there: from X^(0) = 0 it differs
+    x4, _ = ita.ita(y, mask, lam, 4, g)
+    assert not np.allclose(x4, x7)
+
+
+def test_trace_records_the_iterates_norms():
+    # trace["l1"][t] and trace["nnz"][t] are ||X^(t+1)||_1 and the nonzero
+    # count of X^(t+1), the iterate a solve of t + 1 iterations returns.
+    shape = (32, 32)
+    g = csa.Geometry(P, shape)
+    mask = inputs.random_mask(shape, 0.6, seed=21)
+    y = np.where(mask, inputs.random_complex(shape, seed=22), 0)
+    tr = {}
+    ita.ita(y, mask, 0.4, 5, g, trace=tr)
+    assert len(tr["l1"]) == len(tr["nnz"]) == 5
+    for t in range(5):
+        xt, _ = ita.ita(y, mask, 0.4, t + 1, g)
+        assert tr["l1"][t] == float(np.sum(np.abs(xt)))
+        assert tr["nnz"][t] == int(np.count_nonzero(xt))
+        assert 0 < tr["nnz"][t] < xt.size  # the threshold is active
+    # full mask: X^(t) = S(M y) for every t (M G = I), so the trace is flat
+    ones = np.ones(shape, dtype=bool)
+    tr = {}
+    ita.ita(inputs.random_complex(shape, seed=23), ones, 0.4, 3, g, trace=tr)
+    assert abs(tr["l1"][0] - tr["l1"][2]) <= 1e-12 * tr["l1"][0]
+    assert tr["nnz"][0] == tr["nnz"][2]
