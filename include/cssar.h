@@ -160,12 +160,35 @@ int cssar_pack_mask(const cssar_op* op, const void* mask_bytes, void* mask_bits,
  * x_out: N_a x N_r complex64 result X^(iters);
  * resid_hist: NULL or a device array of iters floats receiving ||R^(t)||^2;
  * ws: cssar_workspace_size(op, 1) bytes.  No two of y, x_out, ws may alias.
- * The iterate is kept spatially, per column tile as its support and nonzero
- * values (densely where more than a quarter of a tile is nonzero), so a
- * sparse iterate costs the update pass a read and a write of one array
- * instead of two reads and a write. */
+ * The iterate is kept spatially and sparsely: per group of E elements of a
+ * column (one thread of the update pass), its support and its first two
+ * nonzeros, or all E values where it holds more than two; so a sparse
+ * iterate costs the update pass a read and a write of one array instead of
+ * two reads and a write. */
 int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda,
                     int iters, void* x_out, float* resid_hist, void* ws, void* stream);
+
+/* Options of cssar_ita_solve_ex (zero-initialise; a NULL field keeps the
+ * plain solver's behaviour). */
+typedef struct cssar_solve_opts {
+  const void* x0;     /* starting iterate X^(0) (N_a x N_r complex64, row-major,
+                         device), or NULL for X^(0) = 0 (Algorithm 1) */
+  float* resid_hist;  /* NULL or iters floats: ||R^(t)||^2, t = 0 .. iters-1 */
+  float* l1_hist;     /* NULL or iters floats: ||X^(t+1)||_1 = sum |X_ij| */
+  int* nnz_hist;      /* NULL or iters ints: nonzero count of X^(t+1) */
+} cssar_solve_opts;
+
+/* cssar_ita_solve with the options above.  Warm start: the iteration of
+ * eq. (th2d) / Algorithm 1 goes on from X^(0) = opts->x0, so a solve of
+ * n1 iterations followed by one of n2 from its result gives the image and
+ * residual norms of a solve of n1 + n2 iterations bit for bit (the iterate
+ * kept between passes is rebuilt from x0 exactly as the update pass leaves
+ * it).  Per-iteration metrics: a small pass after each update reads the
+ * sparse iterate (the last one reads x_out) and totals |X_ij| in FP64 in a
+ * fixed order.  opts may be NULL; x0 must not alias y or ws (it may be
+ * x_out: it is read before x_out is written). */
+int cssar_ita_solve_ex(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters,
+                       const cssar_solve_opts* opts, void* x_out, void* ws, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops that forbid allocation): cssar_ita_solve with its

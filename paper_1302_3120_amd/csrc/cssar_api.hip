@@ -268,6 +268,133 @@ int residual_total(cssar_op* op, int ck, const ColArgs& a, bool check, hipStream
   return CSSAR_OK;
 }
 
+// ||X||_1 and the nonzero count of an iterate, per block (FP64 sum, count)
+// into part[2 block], part[2 block + 1]; a one-block kernel totals them.
+// The sparse iterate: one thread per record slot of a wave's area (slots
+// below the wave's record count hold records, packed in lane order); a
+// dense record's thread is the lane of that rank in the wave mask, whose E
+// values lie in the dense tiles at the positions of the update plan
+// (tiles of C columns, T threads per column).
+__global__ __launch_bounds__(256) void sparse_metrics_kernel(const float4* __restrict__ rec,
+                                                             const uint64_t* __restrict__ wmask,
+                                                             const float2* __restrict__ xdense, long long nwaves,
+                                                             int CT, int C, int T, int E, int nr,
+                                                             double* __restrict__ part) {
+  __shared__ double sl[256], sn[256];
+  double l1 = 0.0, nn = 0.0;
+  const long long n = nwaves * 64;
+  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (long long)gridDim.x * blockDim.x) {
+    const long long w = g >> 6;
+    const int slot = (int)(g & 63);
+    const uint64_t m = wmask[w];
+    if (slot >= __builtin_popcountll(m)) continue;
+    const float4 r0 = rec[2 * g], r1 = rec[2 * g + 1];
+    const uint32_t word = __float_as_uint(r0.x);
+    if (word == kDenseWord) {
+      uint64_t mm = m;  // the lane of rank slot
+      for (int q = 0; q < slot; ++q) mm &= mm - 1;
+      const int lane = __builtin_ctzll(mm);
+      const int W = CT / 64;
+      const int tile = (int)(w / W), th = (int)(w % W) * 64 + lane;
+      const Addr ab = col_addr(B4, th / C, tile * C + th % C, T, nr);
+      for (int k = 0; k < E; ++k) {
+        const float2 x = xdense[(ab.voff + (size_t)k * ab.kstep) / 8];
+        const double a = sqrt((double)x.x * x.x + (double)x.y * x.y);
+        l1 += a;
+        nn += a > 0.0 ? 1.0 : 0.0;
+      }
+    } else {
+      const double a0 = sqrt((double)r0.y * r0.y + (double)r0.z * r0.z);
+      const double a1 = __builtin_popcount(word) > 1 ? sqrt((double)r1.x * r1.x + (double)r1.y * r1.y) : 0.0;
+      l1 += a0 + a1;
+      nn += (a0 > 0.0 ? 1.0 : 0.0) + (a1 > 0.0 ? 1.0 : 0.0);
+    }
+  }
+  sl[threadIdx.x] = l1;
+  sn[threadIdx.x] = nn;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sl[threadIdx.x] += sl[threadIdx.x + h];
+      sn[threadIdx.x] += sn[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sl[0];
+    part[2 * blockIdx.x + 1] = sn[0];
+  }
+}
+
+// The same for a row-major (or any dense) array of n complex values.
+__global__ __launch_bounds__(256) void dense_metrics_kernel(const float2* __restrict__ x, long long n,
+                                                            double* __restrict__ part) {
+  __shared__ double sl[256], sn[256];
+  double l1 = 0.0, nn = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float2 v = x[i];
+    const double a = sqrt((double)v.x * v.x + (double)v.y * v.y);
+    l1 += a;
+    nn += a > 0.0 ? 1.0 : 0.0;
+  }
+  sl[threadIdx.x] = l1;
+  sn[threadIdx.x] = nn;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sl[threadIdx.x] += sl[threadIdx.x + h];
+      sn[threadIdx.x] += sn[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sl[0];
+    part[2 * blockIdx.x + 1] = sn[0];
+  }
+}
+
+constexpr int kMetricBlocks = 256;
+
+__global__ __launch_bounds__(256) void metrics_total_kernel(const double* __restrict__ part, float* l1_out,
+                                                            int* nnz_out) {
+  __shared__ double sl[256], sn[256];
+  sl[threadIdx.x] = part[2 * threadIdx.x];
+  sn[threadIdx.x] = part[2 * threadIdx.x + 1];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sl[threadIdx.x] += sl[threadIdx.x + h];
+      sn[threadIdx.x] += sn[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (l1_out) l1_out[0] = (float)sl[0];
+    if (nnz_out) nnz_out[0] = (int)sn[0];
+  }
+}
+
+// ||X||_1 and the nonzero count of the sparse iterate (dense == NULL) or of
+// the dense array x (n values) into l1_out / nnz_out (either may be NULL).
+int iterate_metrics(cssar_op* op, const ColArgs& a, const float2* dense, long long n, float* l1_out,
+                    int* nnz_out, hipStream_t s) {
+  if (!l1_out && !nnz_out) return CSSAR_OK;
+  double* part = (double*)op->partials;  // (the pass partials are consumed by now)
+  if (dense) {
+    hipLaunchKernelGGL(dense_metrics_kernel, dim3(kMetricBlocks), dim3(256), 0, s, dense, n, part);
+  } else {
+    const KernelTable* kt = op->kcol[CK_AS];
+    const long long nwaves = (long long)(op->nr / kt->C) * (kt->CT / 64);
+    hipLaunchKernelGGL(sparse_metrics_kernel, dim3(kMetricBlocks), dim3(256), 0, s, (const float4*)a.xrec,
+                       (const uint64_t*)a.xwmask, (const float2*)a.xdense, nwaves, kt->CT, kt->C, kt->T, kt->E,
+                       op->nr, part);
+  }
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(metrics_total_kernel, dim3(1), dim3(kMetricBlocks), 0, s, (const double*)part, l1_out, nnz_out);
+  HIP_TRY(hipGetLastError());
+  return CSSAR_OK;
+}
+
 int launch_row_adj(cssar_op* op, int conj, const RowArgs& a, hipStream_t s) {
   return timed(op, 13 + conj, s, [&] { return op->kr->row_adj[conj](a, op->grid_adj[conj], s); });
 }
@@ -487,14 +614,16 @@ int cssar_apply_G(cssar_op* op, const void* x, void* y_out, void* ws, void* stre
   return launch_col(op, CK_INV, a, s);
 }
 
-int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters,
-                    void* x_out, float* resid_hist, void* ws, void* stream) {
+int cssar_ita_solve_ex(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters,
+                       const cssar_solve_opts* opts, void* x_out, void* ws, void* stream) {
   int rc = check_op(op);
   if (rc) return rc;
   if (!y || !mask_bits || !x_out || !ws) return fail(CSSAR_EINVAL, "NULL array");
   if (iters < 1) return fail(CSSAR_EINVAL, "iters must be >= 1");
   if (!(lambda >= 0.0f) || !std::isfinite(lambda)) return fail(CSSAR_EINVAL, "lambda must be finite and >= 0");
   if (x_out == y || x_out == ws || ws == y) return fail(CSSAR_EINVAL, "x_out, y and ws must not alias");
+  const cssar_solve_opts o = opts ? *opts : cssar_solve_opts{};
+  if (o.x0 && (o.x0 == ws || o.x0 == y)) return fail(CSSAR_EINVAL, "x0 must not alias y or ws");
   hipStream_t s = (hipStream_t)stream;
   const size_t blk = align256(b4_bytes(op->na, op->nr));
   float2* Xd = (float2*)ws;                      // dense tiles of the sparse iterate (blocked layout)
@@ -505,19 +634,32 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
   a.mask = (const uint32_t*)mask_bits;
   a.sigma = lambda * a.mu;
   set_sparse(op, a, Xd, (char*)ws + 3 * blk);
+  const long long npx = (long long)op->na * op->nr;
+  // R(0) = m o y - m o G X(0): the first pass keeps m o y (Y) for every
+  // residual; from X(0) = 0 it is also F_eta R(0) (P)
+  {
+    ColArgs f = a;
+    f.in0 = (const float2*)y;
+    f.out = P;
+    f.out2 = Y;
+    f.flags = 1 | 4;
+    f.hist_out = o.x0 ? nullptr : o.resid_hist;
+    if ((rc = launch_col(op, CK_FWD, f, s))) return rc;
+    if ((rc = residual_total(op, CK_FWD, f, !o.x0, s))) return rc;
+  }
+  if (o.x0) {
+    // warm start: X(0) as the sparse iterate and F_eta X(0) into P, as an
+    // update pass would have left them
+    ColArgs w = a;
+    w.in0 = (const float2*)o.x0;
+    w.out = P;
+    w.flags = 8;
+    if ((rc = launch_col(op, CK_AS, w, s))) return rc;
+  }
   for (int t = 0; t < iters; ++t) {
     const bool last = t == iters - 1;
-    a.hist_out = resid_hist ? resid_hist + t : nullptr;
-    if (t == 0) {
-      // R(0) = m o y (G X(0) = 0): P = F_eta R, and keep m o y for later residuals
-      ColArgs f = a;
-      f.in0 = (const float2*)y;
-      f.out = P;
-      f.out2 = Y;
-      f.flags = 1 | 4;
-      if ((rc = launch_col(op, CK_FWD, f, s))) return rc;
-      if ((rc = residual_total(op, CK_FWD, f, true, s))) return rc;
-    } else {
+    a.hist_out = o.resid_hist ? o.resid_hist + t : nullptr;
+    if (t > 0 || o.x0) {
       // P = F_eta G X (row chain of G on F_eta X, which the update pass left
       // in P); then R = m o y - m o G X, P = F_eta R
       if ((rc = launch_row(op, row_args(op, P, P, 1), s))) return rc;
@@ -534,11 +676,21 @@ int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float la
     ColArgs u = a;
     u.in1 = P;
     u.out = last ? (float2*)x_out : P;
-    u.flags = (t == 0 ? 1 : 0) | (last ? 2 : 0);
+    u.flags = (t == 0 && !o.x0 ? 1 : 0) | (last ? 2 : 0);
     u.hist_out = nullptr;
     if ((rc = launch_col(op, CK_AS, u, s))) return rc;
+    float* l1 = o.l1_hist ? o.l1_hist + t : nullptr;
+    int* nnz = o.nnz_hist ? o.nnz_hist + t : nullptr;
+    if ((rc = iterate_metrics(op, u, last ? (const float2*)x_out : nullptr, npx, l1, nnz, s))) return rc;
   }
   return CSSAR_OK;
+}
+
+int cssar_ita_solve(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters,
+                    void* x_out, float* resid_hist, void* ws, void* stream) {
+  cssar_solve_opts o{};
+  o.resid_hist = resid_hist;
+  return cssar_ita_solve_ex(op, y, mask_bits, lambda, iters, &o, x_out, ws, stream);
 }
 
 int cssar_profile_enable(cssar_op* op, int on) {

@@ -832,8 +832,8 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
   constexpr int HSC = HT ? hoisted_pass<P>() : -1;
   constexpr int N = P::N, E = P::E, T = P::T, C = P::C, CT = P::CT, W = CT / 64;
   static_assert(E <= 32, "support word holds E bits");
-  const uint32_t rmb = clamp_bytes((size_t)N * a.nr * 8), b4b = clamp_bytes(b4_bytes(N, a.nr));
-  const bool first = a.flags & 1, last = a.flags & 2;
+  const uint32_t b4b = clamp_bytes(b4_bytes(N, a.nr));
+  const bool first = a.flags & 1;
   const int j = tile * C + c;
   const Addr ab = col_addr(B4, b, j, T, a.nr);
   const Buf zin(a.in1, b4b), xd(a.xdense, b4b);
@@ -902,6 +902,27 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
     v[k] = cscale(v[k], f);
     m_new |= keep ? 1u << k : 0u;
   }
+  sparse_store<P, HSC>(a, tile, b, c, lds, tws, hp, v, m_new, lb, lc);
+}
+
+// The end of the sparse-iterate update for X+ in v (support bits m_new):
+// the record or the dense store and the wave's mask, then F_eta X+ into out
+// (B4); or, with flag 2, X+ row-major into out.
+template <class P, int HSC>
+__device__ __forceinline__ void sparse_store(const ColArgs& a, int tile, int b, int c, float2* lds,
+                                             const TwLds& tws, const TwPowers& hp, float2 (&v)[P::E],
+                                             uint32_t m_new, int lb, int lc) {
+  constexpr int N = P::N, E = P::E, T = P::T, C = P::C, CT = P::CT, W = CT / 64;
+  const uint32_t b4b = clamp_bytes(b4_bytes(N, a.nr));
+  const int j = tile * C + c;
+  const Addr ab = col_addr(B4, b, j, T, a.nr);
+  const Buf xd(a.xdense, b4b);
+  const uint32_t ntiles = (uint32_t)(a.nr / C);
+  const Buf recs(a.xrec, clamp_bytes((size_t)ntiles * CT * 32));
+  const Buf wmasks(a.xwmask, clamp_bytes((size_t)ntiles * W * 8));
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t wave_rec = ((uint32_t)tile * CT + (threadIdx.x & ~63u)) * 32u;  // the wave's area
+  const uint32_t wm_off = ((uint32_t)tile * W + wid) * 8u;
   float2 x0 = make_float2(0.f, 0.f), x1 = x0;
   const uint32_t n0 = m_new & (0u - m_new);  // lowest set bit: the first value
   const uint32_t n1 = (m_new ^ n0) & (0u - (m_new ^ n0));  // the second
@@ -912,8 +933,8 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
       x1 = (n1 >> k) & 1u ? v[k] : x1;
     }
   }
-  if (last) {
-    const Buf out(a.out, rmb);
+  if (a.flags & 2) {  // the last iteration: X+ row-major
+    const Buf out(a.out, clamp_bytes((size_t)N * a.nr * 8));
     const Addr ar = col_addr(RM, b, j, T, a.nr);
 #pragma unroll
     for (int k = 0; k < E; ++k) out.st(v[k], ar.voff, k * ar.kstep);
@@ -947,6 +968,28 @@ __device__ __forceinline__ void col_update_sparse(const ColArgs& a, int tile, in
   const Buf out(a.out, b4b);
 #pragma unroll
   for (int k = 0; k < E; ++k) out.st(v[k], ab.voff, k * ab.kstep);
+}
+
+// Warm start of the sparse iterate: X+ given row-major in in0 (its
+// support = its nonzero elements) is stored as the update pass stores its
+// result, and F_eta X+ goes to out, so that a solve goes on from X+ exactly
+// as after an update pass that produced it.
+template <class P, bool HT>
+__device__ __forceinline__ void col_warm_sparse(const ColArgs& a, int tile, int b, int c, float2* lds,
+                                                const float2* twl, const TwPowers& hp) {
+  constexpr int HSC = HT ? hoisted_pass<P>() : -1;
+  constexpr int N = P::N, E = P::E, T = P::T, C = P::C;
+  const Buf xin(a.in0, clamp_bytes((size_t)N * a.nr * 8));
+  const Addr ar = col_addr(RM, b, tile * C + c, T, a.nr);
+  float2 v[E];
+  uint32_t m_new = 0;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    v[k] = xin.f2(ar.voff, k * ar.kstep);
+    m_new |= (v[k].x != 0.0f || v[k].y != 0.0f) ? 1u << k : 0u;
+  }
+  const TwLds tws{twl, twl + 64};
+  sparse_store<P, HSC>(a, tile, b, c, lds, tws, hp, v, m_new, b, c);
 }
 
 // HT: the twiddles of the passes a thread can precompute come from hp
@@ -1251,6 +1294,12 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
     __syncthreads();
   }
   int tile = xcd_logical_block();
+  if constexpr (MODE == COL_AS) {
+    if (a.flags & 8) {  // warm start of the sparse iterate (its own loop)
+      for (; tile < ntiles; tile += gridDim.x) col_warm_sparse<P, HT>(a, tile, b, c, lds, twl, hp);
+      return;
+    }
+  }
   if constexpr (PIPE) {
     if (tile < ntiles) col_preload<P, MODE>(a, tile, b, c, pre);
   }

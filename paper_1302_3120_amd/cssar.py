@@ -30,6 +30,7 @@ SYMBOLS = (
     "cssar_ita_forward", "cssar_ita_backward", "cssar_ita_solve_adaptive",
     "cssar_make_operator_rda", "cssar_operator_chain", "cssar_ita_solve_safeguarded",
     "cssar_azimuth_fm_rate", "cssar_params_with_rates", "cssar_batch_sync_status",
+    "cssar_ita_solve_ex",
 )
 
 PROFILE_KINDS = ("row_M", "row_G", "col_fwd", "col_inv", "col_update_threshold",
@@ -44,6 +45,12 @@ class CssarError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
         self.code = code
+
+
+class SolveOpts(ctypes.Structure):
+    """cssar_solve_opts (device pointers; NULL = unused)."""
+    _fields_ = [("x0", ctypes.c_void_p), ("resid_hist", ctypes.c_void_p),
+                ("l1_hist", ctypes.c_void_p), ("nnz_hist", ctypes.c_void_p)]
 
 
 class Params(ctypes.Structure):
@@ -90,6 +97,7 @@ def lib():
         L.cssar_apply_GH.argtypes = [vp, vp, vp, vp, vp]
         L.cssar_pack_mask.argtypes = [vp, vp, vp, vp]
         L.cssar_ita_solve.argtypes = [vp, vp, vp, f, i, vp, vp, vp, vp]
+        L.cssar_ita_solve_ex.argtypes = [vp, vp, vp, f, i, ctypes.POINTER(SolveOpts), vp, vp, vp]
         L.cssar_sync_status.argtypes = [vp, vp]
         L.cssar_last_error.restype = ctypes.c_char_p
         L.cssar_supported_length.argtypes = [i]
@@ -126,7 +134,8 @@ def lib():
                      "cssar_sync_status", "cssar_supported_length", "cssar_plan_info",
                      "cssar_profile_enable", "cssar_profile_read", "cssar_make_batch",
                      "cssar_destroy_batch", "cssar_batch_set_graph", "cssar_batch_autotune",
-                     "cssar_batch_describe", "cssar_ita_solve_batched", "cssar_batch_sync_status"):
+                     "cssar_batch_describe", "cssar_ita_solve_batched", "cssar_batch_sync_status",
+                     "cssar_ita_solve_ex"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -263,6 +272,26 @@ class Operator:
                                      _ptr(hist) if hist is not None else None,
                                      _ptr(ws), _stream()))
         return (out, hist) if resid else out
+
+    def ita_solve_ex(self, y, mask_bits, lam, iters, x0=None, out=None, ws=None):
+        """cssar_ita_solve_ex: iterative thresholding from X^(0) = x0 (None:
+        0), returning (X^(iters), ||R^(t)||^2, ||X^(t+1)||_1, nonzero count
+        of X^(t+1)), the last three as device tensors of iters entries."""
+        y = self._arr(y, "y")
+        if mask_bits.dtype != torch.int32 or not mask_bits.is_cuda:
+            raise TypeError("mask_bits must come from pack_mask")
+        out = torch.empty_like(y) if out is None else self._arr(out, "out")
+        x0 = None if x0 is None else self._arr(x0, "x0")
+        ws = self._ws(ws, 1, y.device)
+        n = int(iters)
+        hist = torch.empty(max(n, 1), dtype=torch.float32, device=y.device)
+        l1 = torch.empty(max(n, 1), dtype=torch.float32, device=y.device)
+        nnz = torch.empty(max(n, 1), dtype=torch.int32, device=y.device)
+        o = SolveOpts(x0.data_ptr() if x0 is not None else None, hist.data_ptr(), l1.data_ptr(),
+                      nnz.data_ptr())
+        _check(lib().cssar_ita_solve_ex(self._h, _ptr(y), _ptr(mask_bits), float(lam), n,
+                                        ctypes.byref(o), _ptr(out), _ptr(ws), _stream()))
+        return out, hist[:n], l1[:n], nnz[:n]
 
     def ita_solve_adaptive(self, y, mask_bits, k, iters, out=None, ws=None):
         """Iterative thresholding with the step and threshold of Section IV.B
