@@ -34,17 +34,16 @@ PASS_BYTES = {
 # Per pixel per ITA iteration (row G, col R, row M, col A: 80 B) plus the
 # mask (1/8 B): the conventional figure for the fraction of HBM peak.
 ITER_BYTES = 80.125
-# Elements per thread of the sparse-iterate update plans (4096: variant 2,
-# 2048: variant 1, 8192 and the rest: variant 0): one 4-byte support word per
-# E elements.
-UPDATE_E = 16
 
 
 def sparse_update_bytes(nnz_frac):
     """Algorithmic bytes per pixel of the sparse-iterate update pass: Z read
-    and F_eta X+ written (16), the support words read and written (2 x 4/E),
-    and the nonzeros read and written (2 x 8 x the nonzero fraction)."""
-    return 16.0 + 8.0 / UPDATE_E + 16.0 * nnz_frac
+    and F_eta X+ written (16), and the iterate's nonzeros read and written,
+    each as an 8-byte value and a 4-byte position (2 x 12 x the nonzero
+    fraction).  The pass's own format (a wave mask, 32-byte records of the
+    threads with nonzeros) moves somewhat more; that overhead is not
+    counted."""
+    return 16.0 + 24.0 * nnz_frac
 # Kernel symbol of each pass kind; {v} is the plan variant (the residual
 # column pass at 4096 runs variant 1, see column_variant in cssar_api.hip).
 KIND_SYMBOL = {
@@ -166,6 +165,14 @@ def bench_batched(steps, iters, device):
         b.ita_solve(ys, bits, lams, iters, outs=bouts, ws=ws)
 
     t_batch = time_steps(batched, steps, 1)
+    # the launch mode the autotuner did not pick, measured too (graph replay
+    # of the middle iterations, or direct launches)
+    tuned_graph = "graph=1" in b.describe()
+    b.set_graph(not tuned_graph)
+    t_other = time_steps(batched, steps, 1)
+    b.set_graph(tuned_graph)
+    t_graph, t_direct = (t_batch, t_other) if tuned_graph else (t_other, t_batch)
+    b.sync_status()
     worst = 0.0
     for o, r in zip(bouts, outs):
         worst = max(worst, float((o - r).abs().pow(2).sum().sqrt() / r.abs().pow(2).sum().sqrt()))
@@ -176,6 +183,9 @@ def bench_batched(steps, iters, device):
                     f"{px / 1e6:.1f} Mpx, {iters} iterations per step",
         "iterations_per_s": its_b, "plain_loop_iterations_per_s": its_p,
         "speedup_vs_plain_loop": its_b / its_p,
+        "graph_replay_iterations_per_s": steps * iters / t_graph,
+        "direct_launch_iterations_per_s": steps * iters / t_direct,
+        "tuned_launch_mode": "graph" if tuned_graph else "direct",
         "Mpx_iterations_per_s": its_b * px / 1e6,
         "algorithmic_GBs": its_b * px * ITER_BYTES / 1e9,
         "hbm_frac_algorithmic": its_b * px * ITER_BYTES / (HBM_PEAK_GBS * 1e9),
@@ -185,24 +195,27 @@ def bench_batched(steps, iters, device):
 
 
 def bench_grad(steps, device):
-    """Differentiated workload (1024 x 1024, K = 20, checkpoint every 5):
-    forward with checkpoints + reverse pass, against the plain K-iteration
-    solve on the same inputs."""
+    """Differentiated workload (1024 x 1024, 100 point targets, 50 % mask,
+    20 dB, K = 20, checkpoint every 5; raw data through the library's G):
+    forward with checkpoints + reverse pass for L = ||X^(K) - x*||^2,
+    against the plain K-iteration solve on the same inputs, and the
+    gradient's error against the FP64 oracle's, stored for the same recipe
+    (tests/golden/grad_1024.npz, written by tests/golden/grad_1024.py)."""
     import numpy as np
     import torch
     import inputs
     import paper_1302_3120_amd as pk
-    wl = inputs.workload("grad_1024")
+    wl, xt, mask, noise, pick = inputs.gradient_problem_parts("grad_1024", 256)
     shape, K, every = wl["shape"], wl["iters"], wl["every"]
     op = pk.make_operator(inputs.RADAR_STRIPMAP, shape)
-    g = torch.Generator(device=device)
-    g.manual_seed(wl["seed"])
-    y = torch.randn(*shape, dtype=torch.complex64, generator=g, device=device)
-    m = torch.rand(*shape, generator=g, device=device) < wl["mask_rate"]
-    y = torch.where(m, y, torch.zeros_like(y))
-    bits = op.pack_mask(m)
-    lam = float(torch.quantile(op.apply_GH(y).abs().flatten()[: 1 << 20], 0.99))
-    gx = torch.randn(*shape, dtype=torch.complex64, generator=g, device=device)
+    md = torch.from_numpy(mask).to(device)
+    xtd = torch.from_numpy(xt.astype(np.complex64)).to(device)
+    clean = op.apply_G(xtd)
+    s = float((clean.abs() ** 2)[md].mean() / 10.0 ** (wl["snr_db"] / 10.0)) ** 0.5
+    nd = torch.from_numpy(noise.astype(np.complex64)).to(device)
+    y = torch.where(md, clean + s * nd, torch.zeros_like(clean))
+    bits = op.pack_mask(md)
+    lam = float(torch.topk(op.apply_GH(y).abs().flatten(), wl["targets"] + 1).values[-1])
     out = torch.empty_like(y)
     ws = op.workspace(1, device)
 
@@ -210,18 +223,42 @@ def bench_grad(steps, device):
         op.ita_solve(y, bits, lam, K, out=out, ws=ws)
 
     def fwd_bwd():
-        _, ck = op.ita_forward(y, bits, lam, K, every)
-        op.ita_backward(y, bits, lam, K, every, ck, gx)
+        xk, ck = op.ita_forward(y, bits, lam, K, every)
+        op.ita_backward(y, bits, lam, K, every, ck, 2.0 * (xk - xtd))
 
     t_plain = time_steps(plain, steps, 1)
     t_grad = time_steps(fwd_bwd, steps, 1)
-    return {
-        "workload": f"grad_1024: {shape[0]}x{shape[1]}, K = {K} unrolled iterations, checkpoint "
-                    f"every {every}; gradients in y, lambda, K_a, K_r",
+    rec = {
+        "workload": f"grad_1024: {shape[0]}x{shape[1]}, 100 point targets, 50% mask, 20 dB, "
+                    f"K = {K} unrolled iterations, checkpoint every {every}; gradients of "
+                    f"||X(K) - x*||^2 in y, lambda, K_a, K_r",
         "forward_backward_ms": 1e3 * t_grad / steps, "plain_solve_ms": 1e3 * t_plain / steps,
         "cost_vs_plain_solve": t_grad / t_plain,
         "iterations_per_s_forward_backward": steps * K / t_grad,
     }
+    gold_path = os.path.join(ROOT, "tests", "golden", "grad_1024.npz")
+    if os.path.exists(gold_path):
+        gold = np.load(gold_path, allow_pickle=False)
+        yd = y.clone().requires_grad_(True)
+        lt = torch.tensor(lam, dtype=torch.float64, requires_grad=True)
+        ka = torch.tensor(pk.ka_of(inputs.RADAR_STRIPMAP), dtype=torch.float64, requires_grad=True)
+        kr = torch.tensor(float(inputs.RADAR_STRIPMAP["Kr"]), dtype=torch.float64, requires_grad=True)
+        x = pk.ITAUnrolled.apply(yd, lt, ka, kr, md, K, every, inputs.RADAR_STRIPMAP)
+        loss = (x - xtd).abs().pow(2).sum()
+        loss.backward()
+        yb = yd.grad.flatten()[torch.from_numpy(gold["pick"]).to(device)].cpu().numpy()
+        want = gold["ybar"]
+        err = {
+            "lambda": abs(float(lt.grad) - float(gold["lbar"])) / abs(float(gold["lbar"])),
+            "K_a": abs(float(ka.grad) - float(gold["kabar"])) / abs(float(gold["kabar"])),
+            "K_r": abs(float(kr.grad) - float(gold["krbar"])) / abs(float(gold["krbar"])),
+            "y_sampled": float(np.linalg.norm(yb - want) / np.linalg.norm(want)),
+            "loss": abs(float(loss) - float(gold["loss"])) / float(gold["loss"]),
+        }
+        rec["rel_err_vs_oracle"] = err
+        rec["max_rel_err_vs_oracle"] = max(err.values())
+        rec["lambda_rel_diff_vs_oracle"] = abs(lam - float(gold["lam"])) / float(gold["lam"])
+    return rec
 
 
 def bench_adaptive(op, y, bits, k, iters, steps, device):
@@ -477,7 +514,7 @@ def rocprof_summary(stats_dir, fetch_dir, write_dir, n, command, title="ITA pass
                 fk[0], cnt, f_kib, w_kib, fb / 1e6, wb / 1e6))
         machine.append("traffic %s %.0f %.0f" % (kind, fb, wb))
     lines += ["", "Algorithmic bytes per dispatch: 16 B/pixel (row passes), 24 B/pixel (residual "
-                  "column pass), 16 + 8/E + 16 x (nonzero fraction) B/pixel (update pass of the "
+                  "column pass), 16 + 24 x (nonzero fraction) B/pixel (update pass of the "
                   "sparse iterate), 24.125 B/pixel (first column pass: y, mask, two outputs).", "",
               "Machine-readable lines (kind, fetch bytes, write bytes per dispatch, scaled):", ""]
     lines += ["    " + m for m in machine]

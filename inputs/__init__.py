@@ -12,11 +12,11 @@ from .params import (RADAR_STRIPMAP, RADAR_TABLE2_SIM, RADAR_LBAND_STRESS,
 from .scenes import (rng, random_complex, point_targets, targets_to_image,
                      sparse_field, extended_patches, random_mask,
                      circular_noise, batched_shapes)
-from .workloads import WORKLOADS, workload
+from .workloads import WORKLOADS, workload, gradient_problem_parts
 
 __all__ = [
     "RADAR_STRIPMAP", "RADAR_TABLE2_SIM", "RADAR_LBAND_STRESS", "params_with",
     "rng", "random_complex", "point_targets", "targets_to_image",
     "sparse_field", "extended_patches", "random_mask", "circular_noise",
-    "batched_shapes", "WORKLOADS", "workload",
+    "batched_shapes", "WORKLOADS", "workload", "gradient_problem_parts",
 ]

@@ -2,7 +2,10 @@
 SNR, iteration count and seed.  Simulation of the raw data from a scene is
 method arithmetic and lives with whoever consumes these records."""
 
+import numpy as np
+
 from .params import RADAR_STRIPMAP
+from .scenes import circular_noise, point_targets, random_mask, rng, targets_to_image
 
 WORKLOADS = {
     # 256 x 256 stripmap scene, 20 point targets, exact point-target echoes.
@@ -42,3 +45,18 @@ WORKLOADS = {
 def workload(name):
     """A copy of one workload record."""
     return dict(WORKLOADS[name])
+
+
+def gradient_problem_parts(name="grad_1024", samples=256):
+    """The seeded parts of a differentiated workload: the record, the true
+    scene x* (point targets), the mask, unit circular noise and ``samples``
+    sorted sampled positions (flat indices) at which dL/dy is compared."""
+    wl = workload(name)
+    shape = wl["shape"]
+    rows, cols, sig = point_targets(shape, wl["targets"], seed=wl["seed"], amp=wl["amp"])
+    xt = targets_to_image(shape, rows, cols, sig)
+    mask = random_mask(shape, wl["mask_rate"], seed=wl["seed"] + 1)
+    noise = circular_noise(shape, seed=wl["seed"] + 2)
+    sampled = np.flatnonzero(mask.ravel())
+    pick = np.sort(rng(wl["seed"] + 3).choice(sampled, samples, replace=False))
+    return wl, xt, mask, noise, pick
