@@ -502,59 +502,56 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
   };
   if constexpr (cj) {
     apply_quad<E, false>(v, q_eta(), true, 1.0f);
-    // D: for output l and an unwrapped position L = l + m N, the inputs j
-    // with x_j = L - a - (1 + b) j in (-K/2, K/2] are consecutive (at most K
-    // of them); along them x falls by 1 + b, so sin(pi x_c) =
-    // (-1)^c sin(pi (x_0 - c b)) follows by rotating (sin, cos) by -pi b, and
-    // only the candidate nearest x = 0 takes the polynomial.
-    stage(false);
+    // D = C^T as a scatter: input j adds U[j] sinc(t - fr_j) to output
+    // (p_j + t) mod N for each tap t, with p_j + fr_j = j + delta_j and the
+    // weights of C.  The migration slope b = 1/D - 1 lies in [0, 1/2), so
+    // p_j increases with j by 1 or 2 and the positions of one tap are
+    // distinct within each half of the line (their span is under N): one
+    // round per tap and half, the sums formed in LDS in a fixed order.
     const double2 mig = a.rowc1[row];
-    const double a0 = mig.x, b1 = 1.0 + mig.y, inv_b1 = 1.0 / b1;
-    const float b1f = (float)b1, bf = (float)mig.y, inv_b1f = (float)inv_b1;
-    const float2 rot = cis_turns(-0.5 * mig.y);  // (cos, sin) of -pi b
-    // windows span the unwrapped positions pmin .. pmax
-    const int pmin = (int)floor(a0) - K / 2 + 1, pmax = (int)floor(fma(b1, (double)(N - 1), a0)) + K / 2;
+    int pf[E];
+    float fr[E], sp[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-      const int l = b + T * k;
-      float2 acc = make_float2(0.f, 0.f);
-      const int m_lo = (pmin - l + 4 * N + N - 1) / N - 4, m_hi = (pmax - l + 4 * N) / N - 4;
-      for (int m = m_lo; m <= m_hi; ++m) {
-        const double xl = (double)(l + m * N) - a0;
-        const int j0 = max((int)ceil((xl - 0.5 * K) * inv_b1), 0);
-        const int j1 = min((int)ceil((xl + 0.5 * K) * inv_b1) - 1, N - 1);
-        if (j0 > j1) continue;
-        const float x0 = (float)fma(-b1, (double)j0, xl);
-        const float2 cs0 = cis_turns(0.5 * (double)x0);  // (cos, sin) of pi x0
-        float sn = cs0.y, cn = cs0.x;
-        int cnear = (int)rintf(x0 * inv_b1f);
-        const float xn = fmaf(-(float)cnear, b1f, x0);
-        const float wnear = sinc_small(xn);
-        if (!(fabsf(xn) < 0.5f)) cnear = -1;  // no candidate within 1/2 of x = 0
-        const int cnt = j1 - j0;  // candidates c = 0 .. cnt
-        const float2* base = ll + idx(j0);
-        auto cand = [&](int c) {
-          const float x = fmaf(-(float)c, bf, x0 - (float)c);
-          const float sx = (c & 1) ? -sn : sn;
-          float w = sx * __builtin_amdgcn_rcpf(3.14159265f * x);
-          if (c == cnear) w = wnear;
-          const float2 u = FIX ? base[c * LI] : at(j0 + c);  // (the padded order is not linear)
-          acc = make_float2(fmaf(w, u.x, acc.x), fmaf(w, u.y, acc.y));
-          const float sn2 = fmaf(sn, rot.x, cn * rot.y);  // sin(theta - pi b)
-          cn = fmaf(cn, rot.x, -sn * rot.y);               // cos(theta - pi b)
-          sn = sn2;
-        };
-        if constexpr (FIX) {
-#pragma unroll
-          for (int c = 0; c < KT; ++c)
-            if (c <= cnt) cand(c);
-        } else {
-          for (int c = 0; c <= cnt; ++c) cand(c);
-        }
-      }
-      v[k] = acc;
-      __builtin_amdgcn_sched_barrier(0);  // one output at a time (register pressure)
+      const int j = b + T * k;
+      const double pos = fma(mig.y, (double)j, mig.x) + (double)j;
+      const double pfd = floor(pos);
+      fr[k] = (float)(pos - pfd);
+      sp[k] = __builtin_amdgcn_sinf(0.5f * fr[k]) * 0.31830989f;  // sin(pi fr) / pi
+      // |delta| < N/2 (checked on the host): p_j + t stays within (-N, 2N)
+      pf[k] = (int)pfd;
     }
+#pragma unroll
+    for (int k = 0; k < E; ++k) ll[idx(b + T * k)] = make_float2(0.f, 0.f);
+    __syncthreads();
+    // the elements of half h (j < N/2, j >= N/2) of every thread
+    auto tap_round = [&](int t, int h) {
+#pragma unroll
+      for (int k = h * (E / 2); k < (h + 1) * (E / 2); ++k) {
+        int q = pf[k] + t;
+        q = q < 0 ? q + N : (q >= N ? q - N : q);
+        const bool near = t == (fr[k] < 0.5f ? 0 : 1);
+        const float w = near ? sinc_small(fr[k] < 0.5f ? fr[k] : 1.0f - fr[k])
+                             : ((t & 1) ? sp[k] : -sp[k]) * __builtin_amdgcn_rcpf((float)t - fr[k]);
+        float2& d = ll[idx(q)];
+        d = make_float2(fmaf(w, v[k].x, d.x), fmaf(w, v[k].y, d.y));
+      }
+      __syncthreads();
+    };
+    if constexpr (FIX) {
+#pragma unroll
+      for (int t = -KT / 2 + 1; t <= KT / 2; ++t) {
+        tap_round(t, 0);
+        tap_round(t, 1);
+      }
+    } else {
+      for (int t = -K / 2 + 1; t <= K / 2; ++t) {
+        tap_round(t, 0);
+        tap_round(t, 1);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = ll[idx(b + T * k)];
     __syncthreads();
     fft_line<P, false, LI, TwLds, 0, HS>(v, lb, lc, ll, tws, hp);
     apply_quad<E, true>(v, quad_in_slot(0.0, 0.0, a.c_tau, b, T), true, a.scale);
