@@ -34,6 +34,9 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+ROCM_LIB = "/opt/rocm/lib"
+
+
 def common_flags():
     return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
             # no packed FP32 instructions in device code
@@ -74,7 +77,9 @@ def build(jobs=None, verbose=False, report=False):
         print("\n".join(o for o in outs if o.strip()))
     objs = [c[-1] for c in cmds]
     tmp = LIB + ".tmp"
-    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    # roctx: the named host ranges of the entry points and pass launches
+    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, f"-L{ROCM_LIB}",
+          "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}", "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

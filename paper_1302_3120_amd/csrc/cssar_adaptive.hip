@@ -264,6 +264,7 @@ extern "C" {
 int cssar_ita_solve_adaptive(cssar_op* op, const void* y, const void* mask_bits, long k, int iters,
                              void* x_out, float* mu_hist, float* lambda_hist, float* resid_hist, void* ws,
                              void* stream) {
+  const TraceRange tr("cssar_ita_solve_adaptive");
   int rc = check_op(op);
   if (rc) return rc;
   if (!y || !mask_bits || !x_out || !ws) return fail(CSSAR_EINVAL, "NULL array");
@@ -345,6 +346,7 @@ int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bi
                                 double c, double kappa, int max_shrinks, void* x_out, float* mu_hist,
                                 float* lambda_hist, float* resid_hist, int* shrink_hist, void* ws,
                                 void* stream) {
+  const TraceRange tr("cssar_ita_solve_safeguarded");
   int rc = check_op(op);
   if (rc) return rc;
   if (!y || !mask_bits || !x_out || !ws) return fail(CSSAR_EINVAL, "NULL array");

@@ -202,6 +202,13 @@ hipEvent_t take_event(cssar_op* op) {
   return e;
 }
 
+const char* const kPassKindName[CSSAR_PROFILE_KINDS] = {
+    "cssar row M", "cssar row G", "cssar col forward", "cssar col inverse", "cssar col update",
+    "cssar col residual", "cssar col threshold adjoint", "cssar col data adjoint",
+    "cssar col iterate adjoint", "cssar col restricted step", "cssar col step norm",
+    "cssar col value", "cssar col threshold selected", "cssar row adjoint M", "cssar row adjoint G",
+    "cssar select kth", "cssar col update sparse"};
+
 int launch_row(cssar_op* op, const RowArgs& a, hipStream_t s) {
   if (op->chain == CSSAR_CHAIN_RDA)
     return timed(op, a.conj ? 1 : 0, s, [&] { return op->kr->row_rda[a.conj ? 1 : 0](a, op->grid_rda, s); });
@@ -581,6 +588,7 @@ size_t cssar_workspace_size(const cssar_op* op, int mode) {
 }
 
 int cssar_apply_GH(cssar_op* op, const void* y, void* x_out, void* ws, void* stream) {
+  const TraceRange tr("cssar_apply_GH");
   int rc = check_op(op);
   if (rc) return rc;
   if (!y || !x_out || !ws) return fail(CSSAR_EINVAL, "NULL array or workspace");
@@ -598,6 +606,7 @@ int cssar_apply_GH(cssar_op* op, const void* y, void* x_out, void* ws, void* str
 }
 
 int cssar_apply_G(cssar_op* op, const void* x, void* y_out, void* ws, void* stream) {
+  const TraceRange tr("cssar_apply_G");
   int rc = check_op(op);
   if (rc) return rc;
   if (!x || !y_out || !ws) return fail(CSSAR_EINVAL, "NULL array or workspace");
@@ -616,6 +625,7 @@ int cssar_apply_G(cssar_op* op, const void* x, void* y_out, void* ws, void* stre
 
 int cssar_ita_solve_ex(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters,
                        const cssar_solve_opts* opts, void* x_out, void* ws, void* stream) {
+  const TraceRange tr("cssar_ita_solve");
   int rc = check_op(op);
   if (rc) return rc;
   if (!y || !mask_bits || !x_out || !ws) return fail(CSSAR_EINVAL, "NULL array");

@@ -678,6 +678,7 @@ int cssar_batch_describe(const cssar_batch* b, char* buf, int len) {
 
 int cssar_ita_solve_batched(cssar_batch* b, const void* const* ys, const void* const* mask_bits,
                             const float* lambdas, int iters, void* const* x_outs, void* ws, void* stream) {
+  const TraceRange tr("cssar_ita_solve_batched");
   if (!b) return fail(CSSAR_EINVAL, "batch is NULL");
   if (!ys || !mask_bits || !lambdas || !x_outs || !ws) return fail(CSSAR_EINVAL, "NULL argument");
   if (iters < 1) return fail(CSSAR_EINVAL, "iters must be >= 1");
@@ -727,6 +728,7 @@ int cssar_batch_sync_status(cssar_batch* b, void* stream, int* scene) {
 }
 
 int cssar_batch_autotune(cssar_batch* b, void* ws, const char* cache_path, void* stream) {
+  const TraceRange tr("cssar_batch_autotune");
   if (!b) return fail(CSSAR_EINVAL, "batch is NULL");
   if (!ws) return fail(CSSAR_EINVAL, "workspace is NULL");
   hipStream_t s = (hipStream_t)stream;

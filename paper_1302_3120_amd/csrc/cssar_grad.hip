@@ -193,6 +193,7 @@ size_t cssar_grad_workspace_size(const cssar_op* op, int every) {
 
 int cssar_ita_forward(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters, int every,
                       void* x_out, void* ckpt, void* ws, void* stream) {
+  const TraceRange tr("cssar_ita_forward");
   int rc = check_solve_args(op, y, mask_bits, lambda, iters, every);
   if (rc) return rc;
   if (!x_out || !ws || (iters - 1 >= every && !ckpt)) return fail(CSSAR_EINVAL, "NULL array");
@@ -219,6 +220,7 @@ int cssar_ita_forward(cssar_op* op, const void* y, const void* mask_bits, float 
 int cssar_ita_backward(cssar_op* op, const void* y, const void* mask_bits, float lambda, int iters, int every,
                        const void* ckpt, const void* grad_x, void* grad_y, double* grad_scalars, void* ws,
                        void* stream) {
+  const TraceRange tr("cssar_ita_backward");
   int rc = check_solve_args(op, y, mask_bits, lambda, iters, every);
   if (rc) return rc;
   if (!grad_x || !grad_y || !grad_scalars || !ws || (iters - 1 >= every && !ckpt))

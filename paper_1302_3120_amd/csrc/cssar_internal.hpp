@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <string>
 #include <vector>
@@ -81,6 +82,18 @@ ColArgs col_args(const cssar_op* op);
 RowArgs row_args(const cssar_op* op, const void* in, void* out, int conj);
 int check_op(const cssar_op* op);
 
+// A named host range for tracers (rocprofv3 --marker-trace): each entry
+// point's call, and inside it each pass launch by kind.  Without a tracer
+// attached the calls do nothing.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+// Names of the pass kinds of cssar_profile_read (the same order).
+extern const char* const kPassKindName[CSSAR_PROFILE_KINDS];
+
 // An event from the operator's pool (created when the pool is empty).
 hipEvent_t take_event(cssar_op* op);
 // Runs launch(), bracketed by two events on s when profiling is on.  Kind ids
@@ -88,6 +101,7 @@ hipEvent_t take_event(cssar_op* op);
 // 13/14 adjoint row pass (M / G forward), 15 selection of the adaptive threshold.
 template <typename F>
 inline int timed(cssar_op* op, int kind, hipStream_t s, F&& launch) {
+  const TraceRange tr(kind >= 0 && kind < CSSAR_PROFILE_KINDS ? kPassKindName[kind] : "cssar_pass");
   hipEvent_t a = nullptr, b = nullptr;
   if (op->profiling) {
     a = take_event(op);
