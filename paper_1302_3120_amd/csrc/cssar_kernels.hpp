@@ -40,6 +40,9 @@
 
 #include "cssar_device.hpp"
 
+#ifndef RDA_W
+#define RDA_W 4
+#endif
 namespace cssar {
 
 enum Layout { RM = 0, B4 = 1 };
@@ -221,7 +224,7 @@ __device__ __forceinline__ void apply_quad(float2 (&v)[E], const Quad& q, bool c
 // shared through LDS, and the powers of exp(2 pi i B) by products from
 // k' = 0 (at most E/2 of them).  Two evaluations per thread and screen
 // instead of one per element.
-template <int E, bool FREQ>
+template <int E, bool FREQ, bool TAB = true>
 __device__ __forceinline__ void apply_quad_tab(float2 (&v)[E], const Quad& q, const float2* tab, bool conj,
                                                float s) {
   auto slot = [](int kk) { return FREQ ? (kk >= 0 ? kk : kk + E) : kk + E / 2; };
@@ -229,16 +232,18 @@ __device__ __forceinline__ void apply_quad_tab(float2 (&v)[E], const Quad& q, co
   const float2 z0 = cscale(cj(cis_turns(q.A)), s);
   const float2 u = cj(cis_turns(q.B));
   const float2 ub = make_float2(u.x, -u.y);  // u^-1 (|u| = 1)
+  // (TAB false: C = 0, every factor of the table is 1)
+  auto fac = [&](float2 w, int m) { return TAB ? cmul(w, cj(tab[m])) : w; };
   float2 w = z0;
 #pragma unroll
   for (int kk = 0; kk < E / 2; ++kk) {
-    v[slot(kk)] = cmul(v[slot(kk)], cmul(w, cj(tab[kk])));
+    v[slot(kk)] = cmul(v[slot(kk)], fac(w, kk));
     if (kk + 1 < E / 2) w = cmul(w, u);
   }
   w = cmul(z0, ub);
 #pragma unroll
   for (int kk = -1; kk >= -E / 2; --kk) {
-    v[slot(kk)] = cmul(v[slot(kk)], cmul(w, cj(tab[-kk])));
+    v[slot(kk)] = cmul(v[slot(kk)], fac(w, -kk));
     if (kk - 1 >= -E / 2) w = cmul(w, ub);
   }
 }
@@ -308,6 +313,9 @@ struct RowLds {
   // split plans whose LDS lets two workgroups share a CU ask for the
   // registers that allow it (waves per SIMD)
   static constexpr int waves_per_eu = (P::SPLIT && size * 8 <= 78 * 1024) ? 2 * (P::RT / 64) / 4 : 1;
+  // the range-Doppler row pass: two 512-thread workgroups per CU where the
+  // LDS allows (128 VGPRs)
+  static constexpr int rda_waves_per_eu = (!P::SPLIT && P::RT == 512 && size * 8 <= 78 * 1024) ? RDA_W : 1;
 };
 
 // One unit (LR rows) of the row pass of array a:
@@ -454,9 +462,15 @@ __device__ __forceinline__ float sinc_small(float x) {
 // LDS without padding so every tap is an immediate offset, plus a copy of
 // the line's first KT - 1 elements after its end where it fits, so a window
 // never wraps), or 0 for any even count read from a.taps.
+// The two screens come from their quadratic factors: the range-frequency
+// screen's table rtab (exp(2 pi i C m^2), m <= E/2, the same for every
+// line), and the azimuth filter, linear in the range offset, needs none.
+// The twiddle powers of the hoisted pass are formed per unit just before the
+// transforms, so that their registers are free during the interpolation
+// (two workgroups per compute unit).
 template <class P, int CONJ, int KT>
 __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const RowLane<P>& ln, float2* lds,
-                                             const float2* twl, const TwPowers& hp) {
+                                             const float2* twl, const float2* ptab, const float2* rtab) {
   constexpr int HS = hoisted_pass<P>();
   constexpr int N = P::N, E = P::E, T = P::T, LR = P::LR;
   constexpr int LI = RowLds<P>::LI, LS = RowLds<P>::LS;
@@ -479,10 +493,29 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
   asm volatile("" : "+v"(loff));
   float2* ll = lds + loff;  // this line's LDS (interleaved with the unit's other lines)
   const TwLds tws{twl, twl + 64};
+  // the hoisted pass's twiddle powers (the index kept opaque so that they
+  // are formed here, per unit, and not kept across units)
+  auto powers = [&]() {
+    TwPowers hp;
+    if constexpr (HS >= 0) {
+      int hb = b;
+      asm volatile("" : "+v"(hb));
+      hp = hoist_powers<P>(hb, tws, ptab);
+    }
+    return hp;
+  };
   // azimuth filter turns A + B j = (A + B N/2) + B o, o = j - N/2
-  auto q_eta = [&]() {
+  auto eta_screen = [&](bool conj) {
     const double2 az = a.rowc3[row];
-    return quad_in_slot(fma(az.y, 0.5 * N, az.x), az.y, 0.0, b, T);
+    apply_quad_tab<E, false, false>(v, quad_in_slot(fma(az.y, 0.5 * N, az.x), az.y, 0.0, b, T), nullptr, conj,
+                                    1.0f);
+  };
+  // range-frequency screen between the transforms (with 1/N_r; the index
+  // opaque, so that its factors are formed per unit and not held across units)
+  auto tau_screen = [&](bool conj) {
+    int sb = b;
+    asm volatile("" : "+v"(sb));
+    apply_quad_tab<E, true>(v, quad_in_slot(0.0, 0.0, a.c_tau, sb, T), rtab, conj, a.scale);
   };
   const int K = FIX ? KT : a.taps;
   // element j of this line in LDS: unpadded with a fixed tap count (reads of
@@ -501,75 +534,82 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
     __syncthreads();
   };
   if constexpr (cj) {
-    apply_quad<E, false>(v, q_eta(), true, 1.0f);
+    eta_screen(true);
     // D = C^T as a scatter: input j adds U[j] sinc(t - fr_j) to output
     // (p_j + t) mod N for each tap t, with p_j + fr_j = j + delta_j and the
     // weights of C.  The migration slope b = 1/D - 1 lies in [0, 1/2), so
     // p_j increases with j by 1 or 2 and the positions of one tap are
     // distinct within each half of the line (their span is under N): one
-    // round per tap and half, the sums formed in LDS in a fixed order.
+    // round per half and tap (the halves in turn, so that only one half's
+    // positions are held), the sums formed in LDS in a fixed order.
     const double2 mig = a.rowc1[row];
-    int pf[E];
-    float fr[E], sp[E];
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const int j = b + T * k;
-      const double pos = fma(mig.y, (double)j, mig.x) + (double)j;
-      const double pfd = floor(pos);
-      fr[k] = (float)(pos - pfd);
-      sp[k] = __builtin_amdgcn_sinf(0.5f * fr[k]) * 0.31830989f;  // sin(pi fr) / pi
-      // |delta| < N/2 (checked on the host): p_j + t stays within (-N, 2N)
-      pf[k] = (int)pfd;
-    }
 #pragma unroll
     for (int k = 0; k < E; ++k) ll[idx(b + T * k)] = make_float2(0.f, 0.f);
     __syncthreads();
-    // the elements of half h (j < N/2, j >= N/2) of every thread
-    auto tap_round = [&](int t, int h) {
+    int jb = b;  // (opaque: the positions are formed per unit, not kept across units)
+    asm volatile("" : "+v"(jb));
+    constexpr int H = E / 2;
 #pragma unroll
-      for (int k = h * (E / 2); k < (h + 1) * (E / 2); ++k) {
-        int q = pf[k] + t;
-        q = q < 0 ? q + N : (q >= N ? q - N : q);
-        const bool near = t == (fr[k] < 0.5f ? 0 : 1);
-        const float w = near ? sinc_small(fr[k] < 0.5f ? fr[k] : 1.0f - fr[k])
-                             : ((t & 1) ? sp[k] : -sp[k]) * __builtin_amdgcn_rcpf((float)t - fr[k]);
-        float2& d = ll[idx(q)];
-        d = make_float2(fmaf(w, v[k].x, d.x), fmaf(w, v[k].y, d.y));
-      }
-      __syncthreads();
-    };
-    if constexpr (FIX) {
+    for (int h = 0; h < 2; ++h) {
+      int pf[H];
+      float fr[H], sp[H];
 #pragma unroll
-      for (int t = -KT / 2 + 1; t <= KT / 2; ++t) {
-        tap_round(t, 0);
-        tap_round(t, 1);
+      for (int i = 0; i < H; ++i) {
+        const int j = jb + T * (h * H + i);
+        const double pos = fma(mig.y, (double)j, mig.x) + (double)j;
+        const double pfd = floor(pos);
+        fr[i] = (float)(pos - pfd);
+        sp[i] = __builtin_amdgcn_sinf(0.5f * fr[i]) * 0.31830989f;  // sin(pi fr) / pi
+        // |delta| < N/2 (checked on the host): p_j + t stays within (-N, 2N)
+        pf[i] = (int)pfd;
       }
-    } else {
-      for (int t = -K / 2 + 1; t <= K / 2; ++t) {
-        tap_round(t, 0);
-        tap_round(t, 1);
+      auto tap_round = [&](int t) {
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+          int q = pf[i] + t;
+          q = q < 0 ? q + N : (q >= N ? q - N : q);
+          const bool near = t == (fr[i] < 0.5f ? 0 : 1);
+          const float w = near ? sinc_small(fr[i] < 0.5f ? fr[i] : 1.0f - fr[i])
+                               : ((t & 1) ? sp[i] : -sp[i]) * __builtin_amdgcn_rcpf((float)t - fr[i]);
+          const float2 u = v[h * H + i];
+          float2& d = ll[idx(q)];
+          d = make_float2(fmaf(w, u.x, d.x), fmaf(w, u.y, d.y));
+        }
+        __syncthreads();
+      };
+      if constexpr (FIX) {
+#pragma unroll
+        for (int t = -KT / 2 + 1; t <= KT / 2; ++t) tap_round(t);
+      } else {
+        for (int t = -K / 2 + 1; t <= K / 2; ++t) tap_round(t);
       }
     }
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = ll[idx(b + T * k)];
     __syncthreads();
+    const TwPowers hp = powers();
     fft_line<P, false, LI, TwLds, 0, HS>(v, lb, lc, ll, tws, hp);
-    apply_quad<E, true>(v, quad_in_slot(0.0, 0.0, a.c_tau, b, T), true, a.scale);
+    tau_screen(true);
     asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
     fft_line<P, true, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
   } else {
-    fft_line<P, false, LI, TwLds, 0, HS>(v, lb, lc, ll, tws, hp);
-    apply_quad<E, true>(v, quad_in_slot(0.0, 0.0, a.c_tau, b, T), false, a.scale);
-    asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
-    fft_line<P, true, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
+    {
+      const TwPowers hp = powers();
+      fft_line<P, false, LI, TwLds, 0, HS>(v, lb, lc, ll, tws, hp);
+      tau_screen(false);
+      asm volatile("" : "+v"(lb), "+v"(lc), "+v"(loff));
+      fft_line<P, true, LI, TwLds, 0, HS>(v, lb, lc, lds + loff, tws, hp);
+    }
     // C: the K taps of each output's window; sin(pi (t - fr)) =
     // (-1)^(t+1) sin(pi fr), and the tap nearest the position takes the
     // polynomial
     stage(HALO);
     const double2 mig = a.rowc1[row];
+    int jb = b;  // (opaque: the positions are formed per unit, not kept across units)
+    asm volatile("" : "+v"(jb));
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-      const int j = b + T * k;
+      const int j = jb + T * k;
       const double pos = fma(mig.y, (double)j, mig.x) + (double)j;
       const double pf = floor(pos);
       const float fr = (float)(pos - pf);
@@ -599,30 +639,32 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
       __builtin_amdgcn_sched_barrier(0);  // one output at a time (register pressure)
     }
     __syncthreads();
-    apply_quad<E, false>(v, q_eta(), false, 1.0f);
+    eta_screen(false);
   }
 #pragma unroll
   for (int k = 0; k < E; ++k) out.st(v[k], vo, T * k * 32);
 }
 
 template <class P, int CONJ, int KT>
-__global__ __launch_bounds__(P::RT) void row_rda_kernel(RowArgs a) {
+__global__ __launch_bounds__(P::RT, RowLds<P>::rda_waves_per_eu) void row_rda_kernel(RowArgs a) {
   if (a.gate && *a.gate == 0u) return;  // (uniform over the grid)
   __shared__ float2 lds[RowLds<P>::size];
   __shared__ float2 twl[64 + P::N / 64];
   __shared__ float2 ptab[pass_table_size<P>()];
+  __shared__ float2 rtab[P::E / 2 + 1];
   load_twiddle_table<P::N>(twl, a.tw);
   load_pass_table<P>(ptab, a.tw);
+  if (threadIdx.x <= P::E / 2) {  // the range screen's quadratic factors (as quad_in_slot's C)
+    const double C = frac1(a.c_tau * (double)P::T * (double)P::T);
+    rtab[threadIdx.x] = cis_turns(C * (double)(threadIdx.x * threadIdx.x));
+  }
   __syncthreads();
   const RowLane<P> ln;
-  TwPowers hp;
-  if constexpr (hoisted_pass<P>() >= 0)
-    hp = hoist_powers<P>(ln.b, TwLds{twl, twl + 64}, ptab);
   const int units = a.na / P::LR;
   // (it stages whole lines in LDS: the host uses it with unsplit plans only)
   if constexpr (!P::SPLIT) {
     for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x)
-      row_rda_unit<P, CONJ, KT>(a, gi, ln, lds, twl, hp);
+      row_rda_unit<P, CONJ, KT>(a, gi, ln, lds, twl, ptab, rtab);
   }
 }
 
