@@ -40,9 +40,6 @@
 
 #include "cssar_device.hpp"
 
-#ifndef RDA_W
-#define RDA_W 4
-#endif
 namespace cssar {
 
 enum Layout { RM = 0, B4 = 1 };
@@ -315,7 +312,7 @@ struct RowLds {
   static constexpr int waves_per_eu = (P::SPLIT && size * 8 <= 78 * 1024) ? 2 * (P::RT / 64) / 4 : 1;
   // the range-Doppler row pass: two 512-thread workgroups per CU where the
   // LDS allows (128 VGPRs)
-  static constexpr int rda_waves_per_eu = (!P::SPLIT && P::RT == 512 && size * 8 <= 78 * 1024) ? RDA_W : 1;
+  static constexpr int rda_waves_per_eu = (!P::SPLIT && P::RT == 512 && size * 8 <= 78 * 1024) ? 4 : 1;
 };
 
 // One unit (LR rows) of the row pass of array a:
@@ -458,6 +455,32 @@ __device__ __forceinline__ float sinc_small(float x) {
                                 8.3333333e-3f), -1.6666667e-1f), 1.0f);
 }
 
+// The weights sinc(t - fr) of the taps t = -3 .. 4 of an 8-tap window
+// (0 <= fr < 1, sp = sin(pi fr) / pi), except that of the tap nearest the
+// position (0 or 1, the caller's polynomial): sinc(t - fr) = (-1)^(t+1) sp /
+// x_t with x_t = t - fr.  The six taps away from the position share one
+// reciprocal: with the pair products P_m = x_{-m} x_{1+m} (m = 1, 2, 3),
+// sp / x_{-m} = x_{1+m} sp / P_m and sp / x_{1+m} = x_{-m} sp / P_m, and
+// sp / P_m is the product of the other two pairs times sp / (P_1 P_2 P_3).
+// (|x_t| >= 1 for these taps, so no product vanishes.)
+__device__ __forceinline__ void sinc_weights8(float fr, float sp, float (&w)[8]) {
+  const float xm1 = -1.0f - fr, xm2 = -2.0f - fr, xm3 = -3.0f - fr;
+  const float x2 = 2.0f - fr, x3 = 3.0f - fr, x4 = 4.0f - fr;
+  const float p1 = xm1 * x2, p2 = xm2 * x3, p3 = xm3 * x4;
+  const float p12 = p1 * p2;
+  const float r = sp * __builtin_amdgcn_rcpf(p12 * p3);  // sp / (P_1 P_2 P_3)
+  const float q3 = p12 * r, q12 = p3 * r;                 // sp / P_3, sp / (P_1 P_2)
+  const float q1 = p2 * q12, q2 = p1 * q12;               // sp / P_1, sp / P_2
+  w[0] = x4 * q3;    // t = -3
+  w[1] = -x3 * q2;   // t = -2
+  w[2] = x2 * q1;    // t = -1
+  w[3] = sp * __builtin_amdgcn_rcpf(fr);         // t = 0: -sp / (0 - fr)
+  w[4] = sp * __builtin_amdgcn_rcpf(1.0f - fr);  // t = 1
+  w[5] = -xm1 * q1;  // t = 2
+  w[6] = xm2 * q2;   // t = 3
+  w[7] = -xm3 * q3;  // t = 4
+}
+
 // KT: the tap count at compile time (its loops unrolled, the line staged in
 // LDS without padding so every tap is an immediate offset, plus a copy of
 // the line's first KT - 1 elements after its end where it fits, so a window
@@ -543,8 +566,15 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
     // round per half and tap (the halves in turn, so that only one half's
     // positions are held), the sums formed in LDS in a fixed order.
     const double2 mig = a.rowc1[row];
+    // with HALO the taps of a window that passes the line's end go to K - 1
+    // slots after it, added to the line's first elements at the end, so
+    // that every tap is an immediate offset from the window start
 #pragma unroll
-    for (int k = 0; k < E; ++k) ll[idx(b + T * k)] = make_float2(0.f, 0.f);
+    for (int k = 0; k < E; ++k) {
+      const int j = b + T * k;
+      ll[idx(j)] = make_float2(0.f, 0.f);
+      if (HALO && j < K - 1) ll[idx(N + j)] = make_float2(0.f, 0.f);
+    }
     __syncthreads();
     int jb = b;  // (opaque: the positions are formed per unit, not kept across units)
     asm volatile("" : "+v"(jb));
@@ -560,20 +590,26 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
         const double pfd = floor(pos);
         fr[i] = (float)(pos - pfd);
         sp[i] = __builtin_amdgcn_sinf(0.5f * fr[i]) * 0.31830989f;  // sin(pi fr) / pi
-        // |delta| < N/2 (checked on the host): p_j + t stays within (-N, 2N)
-        pf[i] = (int)pfd;
+        // |delta| < N/2 (checked on the host): p_j + t stays within (-N, 2N);
+        // with HALO, the window start modulo N
+        pf[i] = HALO ? ((int)pfd - K / 2 + 1 + 2 * N) % N : (int)pfd;
       }
       auto tap_round = [&](int t) {
 #pragma unroll
         for (int i = 0; i < H; ++i) {
-          int q = pf[i] + t;
-          q = q < 0 ? q + N : (q >= N ? q - N : q);
           const bool near = t == (fr[i] < 0.5f ? 0 : 1);
           const float w = near ? sinc_small(fr[i] < 0.5f ? fr[i] : 1.0f - fr[i])
                                : ((t & 1) ? sp[i] : -sp[i]) * __builtin_amdgcn_rcpf((float)t - fr[i]);
           const float2 u = v[h * H + i];
-          float2& d = ll[idx(q)];
-          d = make_float2(fmaf(w, u.x, d.x), fmaf(w, u.y, d.y));
+          float2* d;
+          if constexpr (HALO) {
+            d = ll + idx(pf[i]) + (t + K / 2 - 1) * LI;  // slot start + tap index
+          } else {
+            int q = pf[i] + t;
+            q = q < 0 ? q + N : (q >= N ? q - N : q);
+            d = ll + idx(q);
+          }
+          *d = make_float2(fmaf(w, u.x, d->x), fmaf(w, u.y, d->y));
         }
         __syncthreads();
       };
@@ -585,7 +621,11 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
       }
     }
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = ll[idx(b + T * k)];
+    for (int k = 0; k < E; ++k) {
+      const int j = b + T * k;
+      v[k] = ll[idx(j)];
+      if (HALO && j < K - 1) v[k] = cadd(v[k], ll[idx(N + j)]);  // the wrapped taps
+    }
     __syncthreads();
     const TwPowers hp = powers();
     fft_line<P, false, LI, TwLds, 0, HS>(v, lb, lc, ll, tws, hp);
@@ -624,7 +664,18 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
         if (t == tn) w = wnear;
         acc = make_float2(fmaf(w, u.x, acc.x), fmaf(w, u.y, acc.y));
       };
-      if constexpr (HALO) {
+      if constexpr (HALO && KT == 8) {
+        const float2* base = ll + idx(q);  // q + KT - 1 < N + KT - 1: inside the copy
+        float w[8];
+        sinc_weights8(fr, sp, w);
+        w[3] = tn == 0 ? wnear : w[3];
+        w[4] = tn == 1 ? wnear : w[4];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float2 u = base[i * LI];
+          acc = make_float2(fmaf(w[i], u.x, acc.x), fmaf(w[i], u.y, acc.y));
+        }
+      } else if constexpr (HALO) {
         const float2* base = ll + idx(q);  // q + KT - 1 < N + KT - 1: inside the copy
 #pragma unroll
         for (int i = 0; i < KT; ++i) tap(i - KT / 2 + 1, base[i * LI]);
