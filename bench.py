@@ -611,8 +611,8 @@ def main():
     op.sync_status()
     its = args.steps * args.iters / dt
     n = shape[0] * shape[1]
-    # the median of five further timed repeats (the survey's protocol), beside
-    # the contract's single region of exactly --steps steps
+    # the median of five further timed repeats, beside the single timed region
+    # of exactly --steps steps
     reps = [args.iters * max(1, args.steps // 2) / time_steps(step, max(1, args.steps // 2), 0)
             for _ in range(5)]
     nnz_frac = float(torch.count_nonzero(out)) / n

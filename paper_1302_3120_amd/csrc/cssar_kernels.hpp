@@ -913,6 +913,12 @@ constexpr uint32_t kDenseWord = 0xFFFFFFFFu;  // (a sparse record has at most tw
 // offsets added to it.
 constexpr uint32_t kPastEnd = 0xF0000000u;
 
+// The end of the sparse-iterate update (defined below).
+template <class P, int HSC>
+__device__ __forceinline__ void sparse_store(const ColArgs& a, int tile, int b, int c, float2* lds,
+                                             const TwLds& tws, const TwPowers& hp, float2 (&v)[P::E],
+                                             uint32_t m_new, int lb, int lc);
+
 // PIPE: Z of this tile was loaded into pre during the previous tile, and Z
 // of the next tile (next >= 0) is loaded into pre during this one.
 template <class P, bool HT, bool PIPE>
