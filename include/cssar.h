@@ -131,9 +131,10 @@ int cssar_destroy_operator(cssar_op* op);
  *           2 N_a N_r bytes of value slots)
  *   mode 2: cssar_ita_solve_adaptive         (four arrays in the blocked layout, the
  *           support bits (4 N_a N_r / E bytes, E the column plan's elements per
- *           thread) and 8.5 KB of selection state)
+ *           thread), 8.6 KB of selection state and its candidate keys, one
+ *           4-byte key per 16 pixels, at least 4096)
  *   mode 3: cssar_ita_solve_safeguarded      (six arrays in the blocked layout, two
- *           sets of support bits and the selection state)
+ *           sets of support bits and the selection state with its keys)
  * The blocked layout holds 4 x 4 blocks of 128 bytes with a 128-byte pad per
  * block row: (N_a/4) (32 N_r + 128) bytes per array.  Returns 0 for a NULL
  * operator or an unknown mode. */

@@ -54,16 +54,30 @@ __global__ __launch_bounds__(kSelectThreads) void select_hist_kernel(const float
   __syncthreads();
   if (st->done) return;  // fewer than k + 1 keys: nothing to select
   const unsigned prefix = st->prefix;
-  const unsigned per_row = 2u * (unsigned)nr;      // float4 (two elements) per block row
-  const unsigned stride = b4_stride(nr) / 16u;     // block-row stride in float4
-  const unsigned total = (unsigned)(na / 4) * per_row;
-  for (unsigned q = blockIdx.x * kSelectThreads + threadIdx.x; q < total; q += gridDim.x * kSelectThreads) {
-    const unsigned row = q / per_row;
-    const float4 p = v[row * stride + (q - row * per_row)];
-    const unsigned k0 = __float_as_uint(fmaf(p.x, p.x, p.y * p.y));
-    const unsigned k1 = __float_as_uint(fmaf(p.z, p.z, p.w * p.w));
-    if (level == 0 || level_prefix(k0, level) == prefix) atomicAdd(&h[level_bin(k0, level)], 1u);
-    if (level == 0 || level_prefix(k1, level) == prefix) atomicAdd(&h[level_bin(k1, level)], 1u);
+  if (level > 0 && st->use_cand) {
+    // every key of the selected first-level bin is among the candidates
+    const unsigned nseg = st->nseg, seg = st->seg;
+    const unsigned* cnt = adapt_cand_counts(st);
+    const unsigned* cand = adapt_candidates(st);
+    for (unsigned g = blockIdx.x; g < nseg; g += gridDim.x) {
+      const unsigned n = cnt[g];  // (at most seg: use_cand)
+      for (unsigned q = threadIdx.x; q < n; q += kSelectThreads) {
+        const unsigned k0 = cand[(size_t)g * seg + q];
+        if (level_prefix(k0, level) == prefix) atomicAdd(&h[level_bin(k0, level)], 1u);
+      }
+    }
+  } else {
+    const unsigned per_row = 2u * (unsigned)nr;    // float4 (two elements) per block row
+    const unsigned stride = b4_stride(nr) / 16u;   // block-row stride in float4
+    const unsigned total = (unsigned)(na / 4) * per_row;
+    for (unsigned q = blockIdx.x * kSelectThreads + threadIdx.x; q < total; q += gridDim.x * kSelectThreads) {
+      const unsigned row = q / per_row;
+      const float4 p = v[row * stride + (q - row * per_row)];
+      const unsigned k0 = __float_as_uint(fmaf(p.x, p.x, p.y * p.y));
+      const unsigned k1 = __float_as_uint(fmaf(p.z, p.z, p.w * p.w));
+      if (level == 0 || level_prefix(k0, level) == prefix) atomicAdd(&h[level_bin(k0, level)], 1u);
+      if (level == 0 || level_prefix(k1, level) == prefix) atomicAdd(&h[level_bin(k1, level)], 1u);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 2048; i += kSelectThreads)
@@ -106,12 +120,30 @@ __global__ __launch_bounds__(kFindThreads) void select_find_kernel(AdaptState* s
     }
   }
   const bool too_few = level == 0 && suf[0] < rank;  // (uniform)
+  // level 0: whether some workgroup of the value pass had more candidates
+  // than its segment holds
+  bool over = false;
+  if (level == 0) {
+    const unsigned nseg = st->nseg, seg = st->seg;
+    const unsigned* cnt = adapt_cand_counts(st);
+    bool mine = nseg == 0u;
+    for (unsigned g = t; g < nseg; g += kFindThreads) mine = mine || cnt[g] > seg;
+    over = __syncthreads_or(mine) != 0;
+  }
   if (t == 0 && too_few && !done) {
     st->done = 1u;
     st->sigma2 = 0.0f;
     st->sigma = 0.0f;
   }
   if (bin != 0xFFFFFFFFu) {
+    if (level == 0) {
+      // the candidates hold the selected bin's keys when it lies in the
+      // window they were taken from and none was dropped; the next value
+      // pass takes the bins next to this one
+      st->use_cand = (bin >= st->wlo && bin <= st->whi && !over) ? 1u : 0u;
+      st->wlo = bin > 0u ? bin - 1u : 0u;
+      st->whi = bin < 2047u ? bin + 1u : 2047u;
+    }
     if (level < 2) {
       st->prefix = level == 0 ? bin : (st->prefix << 11) | bin;
       st->rank = left;
@@ -130,13 +162,15 @@ __global__ __launch_bounds__(kFindThreads) void select_find_kernel(AdaptState* s
       st->prefix = 0u;
       st->rank = st->k1;
       st->done = 0u;
+      st->use_cand = 0u;
     }
   }
 }
 
 // Selection state at the start of a solve: mu_0 = 1 (the support of X(0) = 0
 // is empty), histogram cleared, rank k + 1; the safeguard's constants.
-__global__ void adapt_init_kernel(AdaptState* st, unsigned k1, float* mu0, double c, double shrink) {
+__global__ void adapt_init_kernel(AdaptState* st, unsigned k1, float* mu0, double c, double shrink,
+                                  unsigned nseg, unsigned seg) {
   for (int i = threadIdx.x; i < 2048; i += blockDim.x) st->hist[i] = 0u;
   if (threadIdx.x == 0) {
     st->prefix = 0u;
@@ -153,6 +187,11 @@ __global__ void adapt_init_kernel(AdaptState* st, unsigned k1, float* mu0, doubl
     st->active = 0u;
     st->changed = 0u;
     st->shrinks = 0u;
+    st->wlo = 1u;  // an empty window: the first selection reads V
+    st->whi = 0u;
+    st->nseg = nseg;
+    st->seg = seg;
+    st->use_cand = 0u;
     if (mu0) mu0[0] = 1.0f;
   }
 }
@@ -282,7 +321,8 @@ int cssar_ita_solve_adaptive(cssar_op* op, const void* y, const void* mask_bits,
   float2* Q = (float2*)(w + 3 * blk); // F_eta dX_G, then F_eta G dX_G
   uint32_t* supp = (uint32_t*)(w + 4 * blk);
   AdaptState* st = (AdaptState*)(w + 4 * blk + align256(support_bytes(op)));
-  hipLaunchKernelGGL(adapt_init_kernel, dim3(1), dim3(256), 0, s, st, k1, mu_hist, 0.0, 1.0);
+  hipLaunchKernelGGL(adapt_init_kernel, dim3(1), dim3(256), 0, s, st, k1, mu_hist, 0.0, 1.0,
+                     candidate_segments(op), candidate_segment_keys(op));
   HIP_TRY(hipGetLastError());
   ColArgs a = col_args(op);
   a.y = Y;
@@ -374,7 +414,7 @@ int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bi
   AdaptState* st = (AdaptState*)(w + 6 * blk + 2 * sb);
   const unsigned* active = &st->active;
   hipLaunchKernelGGL(adapt_init_kernel, dim3(1), dim3(256), 0, s, st, k1, mu_hist, c,
-                     1.0 / (kappa * (1.0 - c)));
+                     1.0 / (kappa * (1.0 - c)), candidate_segments(op), candidate_segment_keys(op));
   hipLaunchKernelGGL(zero_words_kernel, dim3(std::max<size_t>(1, std::min<size_t>(1024, sb / 1024))),
                      dim3(256), 0, s, so, sb / 4);
   if (shrink_hist)

@@ -40,6 +40,24 @@ int signed_bin(int k, int n) { return k < (n + 1) / 2 ? k : k - n; }
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
+// One key per 16 pixels: the keys within a factor 2^(3/4) of the selected
+// |V|^2 (three first-level bins), about 3 % of the pixels when the top 1 %
+// lies in a Rayleigh background.
+unsigned candidate_cap(const cssar_op* op) {
+  return (unsigned)std::max<size_t>(4096, (size_t)op->na * op->nr / 16);
+}
+unsigned candidate_segments(const cssar_op* op) {
+  const int g = op->grid_col[CK_V];
+  return g <= kMaxCandSeg ? (unsigned)g : 0u;
+}
+unsigned candidate_segment_keys(const cssar_op* op) {
+  const unsigned n = candidate_segments(op);
+  return n ? candidate_cap(op) / n : 0u;
+}
+size_t adapt_state_bytes(const cssar_op* op) {
+  return align256(sizeof(AdaptState) + ((size_t)kMaxCandSeg + candidate_cap(op)) * sizeof(unsigned));
+}
+
 
 // FP64 coefficient vectors of the three phase screens (turns = radians/2pi).
 //   D(f) = sqrt(1 - (lambda f / (2 v))^2), D_ref = 1 (zero Doppler centroid)
@@ -579,9 +597,9 @@ size_t cssar_workspace_size(const cssar_op* op, int mode) {
     case 1:
       return 3 * blk + sparse_layout(op).bytes;
     case 2:
-      return 4 * blk + align256(support_bytes(op)) + align256(sizeof(AdaptState));
+      return 4 * blk + align256(support_bytes(op)) + adapt_state_bytes(op);
     case 3:
-      return 6 * blk + 2 * align256(support_bytes(op)) + align256(sizeof(AdaptState));
+      return 6 * blk + 2 * align256(support_bytes(op)) + adapt_state_bytes(op);
     default:
       return 0;
   }

@@ -142,6 +142,14 @@ void set_sparse(const cssar_op* op, ColArgs& a, void* dense, void* base, const K
 
 // Bytes of the support bits of the adaptive solver's column passes.
 size_t support_bytes(const cssar_op* op);
+// Selection candidates of the adaptive solvers' value pass: the keys in all
+// (candidate_cap), the workgroups of that pass (0 if more than kMaxCandSeg:
+// no candidates), the keys per workgroup, and the bytes of the selection
+// state with its counts and keys.
+unsigned candidate_cap(const cssar_op* op);
+unsigned candidate_segments(const cssar_op* op);
+unsigned candidate_segment_keys(const cssar_op* op);
+size_t adapt_state_bytes(const cssar_op* op);
 
 // Per Doppler bin, the derivatives of the three phase arguments (radians)
 // with respect to K_a and K_r as polynomials of the centred column offset

@@ -123,8 +123,22 @@ struct AdaptState {
   unsigned active;      // 1 while this iteration's shrink loop goes on (gates its passes)
   unsigned changed;     // the threshold pass found supp X+ != supp X
   unsigned shrinks;     // shrinks taken in this iteration
+  // selection candidates: each workgroup of the value pass (nseg of them)
+  // stores the keys whose first-level bin lies in [wlo, whi] (around the
+  // previous selection's bin) in its own segment of seg keys, and their
+  // count; when the selected bin lies in that window and no segment
+  // overflowed, the later levels read only the candidates (use_cand)
+  unsigned wlo, whi;
+  unsigned nseg, seg;
+  unsigned use_cand;
   unsigned pad2;
 };
+// After an AdaptState: the candidate counts (kMaxCandSeg), then the keys.
+constexpr int kMaxCandSeg = 4096;
+__device__ __forceinline__ unsigned* adapt_cand_counts(AdaptState* st) { return (unsigned*)(st + 1); }
+__device__ __forceinline__ unsigned* adapt_candidates(AdaptState* st) {
+  return (unsigned*)(st + 1) + kMaxCandSeg;
+}
 
 // Marks an unsampled entry of the stored copy of m o y (real part; a NaN
 // with a payload that arithmetic does not produce).
@@ -1275,9 +1289,41 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
     fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);  // V (spatial)
     // first level of the selection of the threshold: histogram of the top
     // 11 bits of |V|^2 (computed as the selection and threshold passes do)
+    auto key = [&](int k) { return __float_as_uint(fmaf(v[k].x, v[k].x, v[k].y * v[k].y)); };
 #pragma unroll
-    for (int k = 0; k < E; ++k)
-      atomicAdd(&hist0[__float_as_uint(fmaf(v[k].x, v[k].x, v[k].y * v[k].y)) >> 21], 1u);
+    for (int k = 0; k < E; ++k) atomicAdd(&hist0[key(k) >> 21], 1u);
+    // the keys in the candidate window, into this workgroup's segment,
+    // packed per wave (an LDS atomic per wave for the wave's slots, the
+    // workgroup's count after the histogram; keys past the segment are
+    // counted, not stored)
+    AdaptState* st = a.ad;
+    const unsigned wlo = st->wlo, whi = st->whi;
+    auto in_win = [&](int k) {
+      const unsigned bin = key(k) >> 21;
+      return bin >= wlo && bin <= whi;
+    };
+    unsigned tot = 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) tot += (unsigned)__popcll(__ballot(in_win(k)));
+    if (tot) {  // (uniform over the wave)
+      const uint64_t act = __ballot(1);
+      const unsigned lane_rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+      unsigned base = 0;
+      if (lane_rank == 0) base = atomicAdd(&hist0[2048], tot);
+      base = __builtin_amdgcn_readfirstlane(base);
+      const unsigned seg = st->seg;
+      unsigned* cand = adapt_candidates(st) + (size_t)blockIdx.x * seg;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const bool in = in_win(k);
+        const uint64_t bal = __ballot(in);
+        const unsigned idx = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (in && idx < seg) cand[idx] = key(k);
+        base += (unsigned)__popcll(bal);
+      }
+    }
   } else if constexpr (MODE == COL_T) {
     // X+ = S_sigma(V): kept where |V|^2 > sigma^2 (sigma^2 the selected
     // (k+1)-th largest |V|^2, computed the same way); support bit = X+ != 0
@@ -1384,9 +1430,10 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
   unsigned chg = 0u;
   float2 pre[P::E];
   // the value pass (adaptive threshold) also counts the first selection level
-  __shared__ unsigned hist0[MODE == COL_V ? 2048 : 1];
+  // (and, after the 2048 bins, its count of selection candidates)
+  __shared__ unsigned hist0[MODE == COL_V ? 2049 : 1];
   if constexpr (MODE == COL_V) {
-    for (int i = threadIdx.x; i < 2048; i += CT) hist0[i] = 0u;
+    for (int i = threadIdx.x; i < 2049; i += CT) hist0[i] = 0u;
     __syncthreads();
   }
   int tile = xcd_logical_block();
@@ -1408,6 +1455,7 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
     __syncthreads();
     for (int i = threadIdx.x; i < 2048; i += CT)
       if (hist0[i]) atomicAdd(&a.ad->hist[i], hist0[i]);
+    if (threadIdx.x == 0 && blockIdx.x < (unsigned)kMaxCandSeg) adapt_cand_counts(a.ad)[blockIdx.x] = hist0[2048];
   }
   if constexpr (MODE == COL_R) {
     // ||R||^2: one partial per block, summed by a one-block kernel launched
