@@ -479,7 +479,12 @@ def rocprof_summary(stats_dir, fetch_dir, write_dir, n, command, title="ITA pass
             if r["Counter_Name"] != counter:
                 continue
             groups.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        copies = {k: v for k, v in groups.items() if "copy" in k.lower()}
+        # the runtime's buffer copy (torch's copy_ of contiguous tensors),
+        # else any copy kernel: elementwise copies of the scene set-up can be
+        # larger than the calibration copy at 8192 x 8192
+        copies = {k: v for k, v in groups.items() if "copybuffer" in k.lower()}
+        if not copies:
+            copies = {k: v for k, v in groups.items() if "copy" in k.lower()}
         if not copies:
             raise SystemExit("no copy kernel in " + d)
         # the calibration copy is the largest copy dispatch of the run
