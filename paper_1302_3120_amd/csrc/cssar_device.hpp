@@ -156,6 +156,27 @@ __device__ __forceinline__ void dft16(float2* a, const float2* W = nullptr) {
     for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = t[4 * k1 + k2];
 }
 
+// 24-point DFT as 3 x 8 with coprime factors (Good-Thomas): input n = (8 n1
+// + 3 n2) mod 24 and output k = (16 k1 + 9 k2) mod 24 make the exponent
+// n k = 8 n1 k1 + 3 n2 k2 (mod 24), so X[k] is a 3-point DFT over n1 of
+// 8-point DFTs over n2, with no twiddles between them.
+template <bool INV>
+__device__ __forceinline__ void dft24(float2* a) {
+  float2 t[3][8];
+#pragma unroll
+  for (int n1 = 0; n1 < 3; ++n1)
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) t[n1][n2] = a[(8 * n1 + 3 * n2) % 24];
+#pragma unroll
+  for (int n1 = 0; n1 < 3; ++n1) dft8<INV>(t[n1]);
+#pragma unroll
+  for (int k2 = 0; k2 < 8; ++k2) {
+    dft3<INV>(t[0][k2], t[1][k2], t[2][k2]);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) a[(16 * k1 + 9 * k2) % 24] = t[k1][k2];
+  }
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dft_reg(float2* a) {
   if constexpr (R == 2) {
@@ -166,6 +187,8 @@ __device__ __forceinline__ void dft_reg(float2* a) {
     dft4<INV>(a[0], a[1], a[2], a[3]);
   } else if constexpr (R == 8) {
     dft8<INV>(a);
+  } else if constexpr (R == 24) {
+    dft24<INV>(a);
   } else {
     static_assert(R == 16, "radix");
     dft16<INV>(a);

@@ -46,14 +46,14 @@ CSSAR_PLAN(128, 0, 16, 16, 256, 16, 8)
 CSSAR_PLAN(256, 0, 16, 16, 256, 16, 16)
 CSSAR_PLAN(512, 0, 8, 16, 256, 8, 8, 8)
 CSSAR_PLAN(512, 1, 16, 16, 256, 16, 16, 2)
-CSSAR_PLAN(768, 0, 24, 16, 256, 3, 8, 8, 4)
+CSSAR_PLAN(768, 0, 24, 16, 256, 24, 8, 4)
 CSSAR_PLAN(1024, 0, 16, 8, 256, 16, 16, 4)
 CSSAR_PLAN(1024, 1, 32, 16, 256, 16, 16, 4)
-CSSAR_PLAN(1536, 0, 24, 4, 128, 3, 8, 8, 8)
-CSSAR_PLAN(1536, 1, 24, 8, 256, 3, 8, 8, 8)
+CSSAR_PLAN(1536, 0, 24, 4, 128, 24, 8, 8)
+CSSAR_PLAN(1536, 1, 24, 8, 256, 24, 8, 8)
 CSSAR_PLAN(2048, 0, 16, 8, 256, 16, 16, 8)
 CSSAR_PLAN(2048, 1, 16, 4, 256, 16, 16, 8)
-CSSAR_PLAN(3072, 0, 24, 4, 512, 3, 8, 8, 8, 2)
+CSSAR_PLAN(3072, 0, 24, 4, 512, 24, 8, 8, 2)
 CSSAR_PLAN(4096, 0, 16, 4, 512, 16, 16, 16)
 CSSAR_PLAN(4096, 1, 32, 4, 256, 16, 16, 16)
 // two-column tiles (half the LDS of a four-column tile: two workgroups per CU)
