@@ -177,6 +177,36 @@ __device__ __forceinline__ void dft24(float2* a) {
   }
 }
 
+// 32-point DFT from the 16-point DFTs E, O of the even and odd inputs:
+// X[k] = E[k] + w32^k O[k], X[k + 16] = E[k] - w32^k O[k], w32^k =
+// (cos(k pi/16), -sin(k pi/16)), both from cos(j pi/16), j <= 8.
+template <bool INV>
+__device__ __forceinline__ void dft32(float2* a) {
+  constexpr float C[9] = {1.0f,
+                          0.98078528040323043f,
+                          0.92387953251128674f,
+                          0.83146961230254524f,
+                          0.70710678118654752f,
+                          0.55557023301960222f,
+                          0.38268343236508977f,
+                          0.19509032201612826f,
+                          0.0f};
+  float2 e[16], o[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    e[i] = a[2 * i];
+    o[i] = a[2 * i + 1];
+  }
+  dft16<INV>(e);
+  dft16<INV>(o);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const float c = k <= 8 ? C[k] : -C[16 - k];
+    const float sn = k <= 8 ? C[8 - k] : C[k - 8];
+    fma_pair<INV>(e[k], make_float2(c, -sn), o[k], a[k], a[k + 16]);
+  }
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dft_reg(float2* a) {
   if constexpr (R == 2) {
@@ -189,6 +219,8 @@ __device__ __forceinline__ void dft_reg(float2* a) {
     dft8<INV>(a);
   } else if constexpr (R == 24) {
     dft24<INV>(a);
+  } else if constexpr (R == 32) {
+    dft32<INV>(a);
   } else {
     static_assert(R == 16, "radix");
     dft16<INV>(a);

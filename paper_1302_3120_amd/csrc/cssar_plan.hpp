@@ -61,7 +61,7 @@ CSSAR_PLAN(4096, 2, 16, 2, 512, 16, 16, 16)
 CSSAR_PLAN(8192, 0, 16, 2, 512, 16, 16, 16, 2)
 // 8192-point lines through half the LDS: four-column tiles, and two rows per
 // row-pass workgroup (two workgroups per CU)
-CSSAR_PLAN_S(8192, 1, 32, 4, 512, true, 16, 16, 16, 2)
+CSSAR_PLAN_S(8192, 1, 32, 4, 512, true, 16, 16, 32)
 
 #undef CSSAR_PLAN
 #undef CSSAR_PLAN_S
