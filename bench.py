@@ -529,6 +529,28 @@ def rocprof_summary(stats_dir, fetch_dir, write_dir, n, command, title="ITA pass
     return "\n".join(lines) + "\n"
 
 
+def marker_summary(marker_dir, n, command):
+    """Text summary of the library's roctx ranges (rocprofv3 --marker-trace)."""
+    lines = ["# roctx ranges of one solve at %dx%d complex64 (rocprofv3 --marker-trace)" % (n, n), "",
+             "Command (from the repository root, on one MI355X):", ""]
+    lines += ["    " + c for c in command]
+    lines += ["", "The library pushes a named host range around each entry point (`cssar_ita_solve`, "
+                  "`cssar_apply_G`, ...) and",
+              "around each pass launch (`cssar row M`, `cssar col residual`, ...).  The ranges time "
+              "the host side of",
+              "the call (argument checks and the asynchronous launches), not the kernels: the kernel "
+              "trace of the same",
+              "run gives those.", "",
+              "| range | calls | total us | average us | min us | max us |", "|---|---|---|---|---|---|"]
+    rows = sorted(_rows(os.path.join(marker_dir, "**", "*marker_api_stats.csv")),
+                  key=lambda r: -float(r["TotalDurationNs"]))
+    for r in rows:
+        lines.append("| %s | %s | %.1f | %.1f | %.1f | %.1f |" % (
+            r["Name"], r["Calls"], float(r["TotalDurationNs"]) / 1e3, float(r["AverageNs"]) / 1e3,
+            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
+    return "\n".join(lines) + "\n"
+
+
 def load_traffic():
     """Per-kind scaled HBM bytes per dispatch from the committed summary, or
     None when it is missing or the kernel sources changed since."""
@@ -578,8 +600,13 @@ def main():
                     help="title of the --rocprof-summary text")
     ap.add_argument("--sq-dir", action="append", default=[],
                     help="rocprofv3 --pmc SQ_* output directories for the --rocprof-summary text")
+    ap.add_argument("--marker-summary", metavar="MARKER_DIR",
+                    help="print a text summary of the roctx ranges of a rocprofv3 --marker-trace run")
     args = ap.parse_args()
 
+    if args.marker_summary:
+        print(marker_summary(args.marker_summary, args.size, args.command))
+        return
     if args.rocprof_summary:
         print(rocprof_summary(*args.rocprof_summary, args.size, args.command, args.summary_title,
                               args.sq_dir))
