@@ -415,7 +415,9 @@ __global__ __launch_bounds__(P::RT, RowLds<P>::waves_per_eu) void row_pass_kerne
     hp = hoist_powers<P>(ln.b, TwLds{twl, twl + 64}, ptab);
   const int units = a.na / P::LR;  // N_a is a multiple of LR
   int par = 0;
-  for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x) {
+  // units of one or two rows read part of each 128-byte block: the units of a
+  // block row run on one XCD, whose L2 serves the block to all of them
+  for (int gi = P::LR <= 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x) {
     // the barrier of the fill also orders this unit's table against the
     // previous reader of the same buffer (two units ago)
     float2* qt = qtab + par * RowQTab<P>::size;
@@ -726,9 +728,10 @@ __global__ __launch_bounds__(P::RT, RowLds<P>::rda_waves_per_eu) void row_rda_ke
   __syncthreads();
   const RowLane<P> ln;
   const int units = a.na / P::LR;
-  // (it stages whole lines in LDS: the host uses it with unsplit plans only)
+  // (it stages whole lines in LDS: the host uses it with unsplit plans only;
+  // the units of a block row on one XCD, as in the row pass)
   if constexpr (!P::SPLIT) {
-    for (int gi = P::LR == 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x)
+    for (int gi = P::LR <= 2 ? xcd_logical_block() : (int)blockIdx.x; gi < units; gi += gridDim.x)
       row_rda_unit<P, CONJ, KT>(a, gi, ln, lds, twl, ptab, rtab);
   }
 }
