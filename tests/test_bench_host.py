@@ -1,5 +1,6 @@
 """Host-side checks of bench.py (no GPU): the one-GPU rule, the rocprofv3
-summary parser on small synthetic CSV files, and the counter-traffic loader's
+summary parser on small synthetic CSV files (the calibration copy, the roctx
+ranges), and the counter-traffic loader's
 digest check."""
 
 import csv
@@ -63,3 +64,37 @@ def test_traffic_is_null_for_other_kernel_sources(tmp_path, monkeypatch):
     assert bench.load_traffic() is None
     f.write_text("    traffic col_residual 1 2\n    kernel_sources_sha256 %s\n" % bench.kernel_source_digest())
     assert bench.load_traffic() == {"col_residual": 3.0}
+
+
+def test_calibration_takes_the_buffer_copy_over_larger_copies(tmp_path):
+    # at 8192 x 8192 the scene set-up runs elementwise copies larger than the
+    # 256 MiB calibration copy; the runtime's buffer copy is the calibration
+    n = 8192
+    sym_r = "void cssar::" + bench.kind_symbol("col_residual", n) + "(cssar::ColArgs)"
+    _write(str(tmp_path / "s" / "run_kernel_stats.csv"),
+           ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs"],
+           [[sym_r, 10, 1e6, 1e5, 100.0, 9e4, 1.1e5]])
+    cal = bench.CAL_MIB * 1024
+    big = "void at::native::elementwise_kernel<128, 4, direct_copy_kernel_cuda>"
+    for d, counter in (("f", "FETCH_SIZE"), ("w", "WRITE_SIZE")):
+        _write(str(tmp_path / d / "run_counter_collection.csv"),
+               ["Kernel_Name", "Counter_Name", "Counter_Value"],
+               [["__amd_rocclr_copyBuffer", counter, cal / 2.0], [big, counter, 4 * cal],
+                [sym_r, counter, 1000.0]])
+    text = bench.rocprof_summary(str(tmp_path / "s"), str(tmp_path / "f"), str(tmp_path / "w"), n,
+                                 ["cmd"])
+    assert "scale factor 2.0000" in text
+    lines = {l.split()[1]: l.split() for l in text.splitlines() if l.strip().startswith("traffic ")}
+    assert float(lines["col_residual"][2]) == pytest.approx(1000 * 1024 * 2.0)
+
+
+def test_marker_summary_lists_ranges_by_total_time(tmp_path):
+    _write(str(tmp_path / "m" / "run_marker_api_stats.csv"),
+           ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs", "StdDev"],
+           [["cssar row M", 4, 2000.0, 500.0, 20.0, 400.0, 600.0, 1.0],
+            ["cssar_ita_solve", 1, 8000.0, 8000.0, 80.0, 8000.0, 8000.0, 0.0]])
+    text = bench.marker_summary(str(tmp_path / "m"), 4096, ["cmd"])
+    rows = [l for l in text.splitlines() if l.startswith("| cssar")]
+    assert rows[0].startswith("| cssar_ita_solve | 1 | 8.0 |")
+    assert rows[1].startswith("| cssar row M | 4 | 2.0 | 0.5 |")
+    assert "    cmd" in text
