@@ -1,7 +1,6 @@
 """Host-side checks of bench.py (no GPU): the one-GPU rule, the rocprofv3
-summary parser on small synthetic CSV files (the calibration copy, the roctx
-ranges), and the counter-traffic loader's
-digest check."""
+summary parsers on small synthetic CSV files (the calibration copy, the roctx
+ranges), and the counter-traffic loader's digest check."""
 
 import csv
 import os
