@@ -60,7 +60,7 @@ def _gpu_grad(params, shape, xt, y, mask, lam, K, every, dev):
     x = pk.ITAUnrolled.apply(yd, lt, ka, kr, m, K, every, params)
     loss = (x - _d(xt, dev)).abs().pow(2).sum()
     loss.backward()
-    return (float(loss), yd.grad.cpu().numpy().astype(np.complex128), float(lt.grad),
+    return (float(loss.detach()), yd.grad.cpu().numpy().astype(np.complex128), float(lt.grad),
             float(ka.grad), float(kr.grad))
 
 
