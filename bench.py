@@ -253,7 +253,7 @@ def bench_grad(steps, device):
             "K_a": abs(float(ka.grad) - float(gold["kabar"])) / abs(float(gold["kabar"])),
             "K_r": abs(float(kr.grad) - float(gold["krbar"])) / abs(float(gold["krbar"])),
             "y_sampled": float(np.linalg.norm(yb - want) / np.linalg.norm(want)),
-            "loss": abs(float(loss) - float(gold["loss"])) / float(gold["loss"]),
+            "loss": abs(float(loss.detach()) - float(gold["loss"])) / float(gold["loss"]),
         }
         rec["rel_err_vs_oracle"] = err
         rec["max_rel_err_vs_oracle"] = max(err.values())
