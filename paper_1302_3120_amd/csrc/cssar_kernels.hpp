@@ -608,7 +608,12 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
         sp[i] = __builtin_amdgcn_sinf(0.5f * fr[i]) * 0.31830989f;  // sin(pi fr) / pi
         // |delta| < N/2 (checked on the host): p_j + t stays within (-N, 2N);
         // with HALO, the window start modulo N
-        pf[i] = HALO ? ((int)pfd - K / 2 + 1 + 2 * N) % N : (int)pfd;
+        if constexpr (HALO) {
+          const unsigned qs = (unsigned)((int)pfd - K / 2 + 1 + 2 * N);  // (positive)
+          pf[i] = (int)((N & (N - 1)) == 0 ? (qs & (unsigned)(N - 1)) : qs % (unsigned)N);
+        } else {
+          pf[i] = (int)pfd;
+        }
       }
       auto tap_round = [&](int t) {
 #pragma unroll
@@ -672,8 +677,10 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
       const float sp = __builtin_amdgcn_sinf(0.5f * fr) * 0.31830989f;  // sin(pi fr) / pi
       const int tn = fr < 0.5f ? 0 : 1;
       const float wnear = sinc_small(fr < 0.5f ? fr : 1.0f - fr);
-      // |delta| < N/2 (checked on the host), so the window start is > -2N
-      int q = ((int)pf - K / 2 + 1 + 2 * N) % N;
+      // |delta| < N/2 (checked on the host), so the window start is > -2N and
+      // the sum below is positive
+      const unsigned qs = (unsigned)((int)pf - K / 2 + 1 + 2 * N);
+      int q = (int)((N & (N - 1)) == 0 ? (qs & (unsigned)(N - 1)) : qs % (unsigned)N);
       float2 acc = make_float2(0.f, 0.f);
       auto tap = [&](int t, float2 u) {
         float w = ((t & 1) ? sp : -sp) * __builtin_amdgcn_rcpf((float)t - fr);
@@ -682,15 +689,16 @@ __device__ __forceinline__ void row_rda_unit(const RowArgs& a, int gi, const Row
       };
       if constexpr (HALO && KT == 8) {
         const float2* base = ll + idx(q);  // q + KT - 1 < N + KT - 1: inside the copy
+        float2 u[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) u[i] = base[i * LI];
+        __builtin_amdgcn_sched_barrier(0);  // the reads in flight during the weights
         float w[8];
         sinc_weights8(fr, sp, w);
         w[3] = tn == 0 ? wnear : w[3];
         w[4] = tn == 1 ? wnear : w[4];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const float2 u = base[i * LI];
-          acc = make_float2(fmaf(w[i], u.x, acc.x), fmaf(w[i], u.y, acc.y));
-        }
+        for (int i = 0; i < 8; ++i) acc = make_float2(fmaf(w[i], u[i].x, acc.x), fmaf(w[i], u[i].y, acc.y));
       } else if constexpr (HALO) {
         const float2* base = ll + idx(q);  // q + KT - 1 < N + KT - 1: inside the copy
 #pragma unroll
