@@ -197,14 +197,15 @@ __global__ void adapt_init_kernel(AdaptState* st, unsigned k1, float* mu0, doubl
 }
 
 // What the one-block kernel after a pass does with the pass's total.
-enum AdaptTotal { AT_NUM = 0, AT_CHANGE, AT_STEP, AT_BOUND };
+enum AdaptTotal { AT_NUM = 0, AT_CHANGE, AT_STEP, AT_BOUND, AT_DNUM };
 
 // Totals of the passes of the adaptive iteration from their per-block
 // partials (summed in the order of the last-block reductions; bit 0 of
 // status if not finite), and what follows from them:
 //   AT_NUM    (pass D): ||dX_G||^2 into num;
-//   AT_CHANGE (pass T, safeguard): ||F_eta (X+ - X)||^2 into dnum; the shrink
-//             loop goes on after a support change;
+//   AT_CHANGE (pass T, safeguard, no partials): the shrink loop goes on
+//             after a support change;
+//   AT_DNUM   (the difference pass, safeguard): ||F_eta (X+ - X)||^2 into dnum;
 //   AT_STEP   (pass N): the step of Section IV.B (eq. (mure) read as the
 //             normalized step) mu = ||dX_G||^2 / ||m o G dX_G||^2, and mu = 1
 //             when either is 0 (empty support: the same ratio over the whole
@@ -232,9 +233,10 @@ __global__ __launch_bounds__(256) void adapt_total_kernel(const float* __restric
     if (which == AT_NUM) {
       st->num = t;
     } else if (which == AT_CHANGE) {
-      st->dnum = t;
       st->active = st->changed ? 1u : 0u;
       st->changed = 0u;
+    } else if (which == AT_DNUM) {
+      st->dnum = t;
     } else if (which == AT_STEP) {
       const double num = st->num;
       const double mu = (num == 0.0 || !(t > 0.0)) ? 1.0 : num / t;
@@ -257,12 +259,43 @@ __global__ __launch_bounds__(256) void adapt_total_kernel(const float* __restric
   }
 }
 
+// The total of nblocks partials (the pass ck's grid when nblocks < 0).
 int adapt_total(cssar_op* op, int ck, int which, AdaptState* st, const unsigned* gate, float* mu_out,
-                int* count_out, hipStream_t s) {
-  hipLaunchKernelGGL(adapt_total_kernel, dim3(1), dim3(256), 0, s, (const float*)op->partials, op->grid_col[ck],
-                     st, which, op->counter + 1, gate, 1.0 / op->na, mu_out, count_out);
+                int* count_out, hipStream_t s, int nblocks = -1) {
+  hipLaunchKernelGGL(adapt_total_kernel, dim3(1), dim3(256), 0, s, (const float*)op->partials,
+                     nblocks < 0 ? op->grid_col[ck] : nblocks, st, which, op->counter + 1, gate, 1.0 / op->na,
+                     mu_out, count_out);
   HIP_TRY(hipGetLastError());
   return CSSAR_OK;
+}
+
+// Safeguard, after a support change: D = F_eta X+ - F_eta X (blocked
+// layout, pads skipped; X = 0 with zero_x) and per-block partials of
+// ||D||^2 (one plain store per block, totalled by the one-block kernel).
+constexpr int kDiffThreads = 256;
+__global__ __launch_bounds__(kDiffThreads) void diff_norm_kernel(const float4* __restrict__ xn,
+                                                                 const float4* __restrict__ x, float4* d,
+                                                                 int na, int nr, int zero_x, float* partials,
+                                                                 const unsigned* gate) {
+  if (gate && *gate == 0u) return;  // (uniform over the grid)
+  __shared__ float red[kDiffThreads / 64];
+  const unsigned per_row = 2u * (unsigned)nr;    // float4 (two elements) per block row
+  const unsigned stride = b4_stride(nr) / 16u;   // block-row stride in float4
+  const unsigned total = (unsigned)(na / 4) * per_row;
+  float acc = 0.f;
+  for (unsigned q = blockIdx.x * kDiffThreads + threadIdx.x; q < total; q += gridDim.x * kDiffThreads) {
+    const unsigned row = q / per_row;
+    const size_t i = (size_t)row * stride + (q - row * per_row);
+    float4 v = xn[i];
+    if (!zero_x) {
+      const float4 u = x[i];
+      v = make_float4(v.x - u.x, v.y - u.y, v.z - u.z, v.w - u.w);
+    }
+    d[i] = v;
+    acc = fmaf(v.x, v.x, fmaf(v.y, v.y, fmaf(v.z, v.z, fmaf(v.w, v.w, acc))));
+  }
+  const float part = block_sum<kDiffThreads>(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = part;
 }
 
 // Zero n 32-bit words (a kernel rather than a memset node, so the solve can
@@ -424,6 +457,8 @@ int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bi
   a.y = Y;
   a.mask = (const uint32_t*)mask_bits;
   a.ad = st;
+  const int diff_grid =
+      std::max(1, std::min(std::min(op->cus * 4, kMaxPartials), (op->na / 4) * op->nr / 2 / kDiffThreads + 1));
   for (int t = 0; t < iters; ++t) {
     a.hist_out = resid_hist ? resid_hist + t : nullptr;
     a.supp = so;  // the support of X (read by D)
@@ -472,21 +507,24 @@ int cssar_ita_solve_safeguarded(cssar_op* op, const void* y, const void* mask_bi
       v.gate = gate;
       if ((rc = launch_col(op, CK_V, v, s))) return rc;
       if ((rc = select_threshold(op, Q, st, lambda_hist ? lambda_hist + t : nullptr, s, gate))) return rc;
-      ColArgs x = a;  // X+ = S_sigma(V) -> F_eta X+; support change; F_eta (X+ - X)
+      ColArgs x = a;  // X+ = S_sigma(V) -> F_eta X+; support change
       x.in0 = Q;
-      x.in1 = X;
       x.out = Xn;
-      x.out2 = Df;
       x.supp = sn;
       x.supp_old = so;
       x.out3 = (float2*)x_out;  // the last iteration's X+ (each round overwrites it)
-      x.flags = 4 | (t == 0 ? 1 : 0) | (t == iters - 1 ? 16 : 0);
+      x.flags = 4 | (t == iters - 1 ? 16 : 0);
       x.hist_out = nullptr;
       x.gate = gate;
       if ((rc = launch_col(op, CK_T, x, s))) return rc;
-      if ((rc = adapt_total(op, CK_T, AT_CHANGE, st, gate, nullptr, nullptr, s))) return rc;
+      if ((rc = adapt_total(op, CK_T, AT_CHANGE, st, gate, nullptr, nullptr, s, 0))) return rc;
       if (round == max_shrinks) break;
-      RowArgs g = row_args(op, Df, Df, 1);  // F_eta G(X+ - X), after a support change
+      // after a support change: F_eta (X+ - X) and ||X+ - X||^2 (Parseval)
+      hipLaunchKernelGGL(diff_norm_kernel, dim3(diff_grid), dim3(kDiffThreads), 0, s, (const float4*)Xn,
+                         (const float4*)X, (float4*)Df, op->na, op->nr, t == 0 ? 1 : 0, op->partials, active);
+      HIP_TRY(hipGetLastError());
+      if ((rc = adapt_total(op, CK_T, AT_DNUM, st, active, nullptr, nullptr, s, diff_grid))) return rc;
+      RowArgs g = row_args(op, Df, Df, 1);  // F_eta G(X+ - X)
       g.gate = active;
       if ((rc = launch_row(op, g, s))) return rc;
       ColArgs b = a;  // the bound; shrink mu or end the loop

@@ -158,12 +158,11 @@ struct ColArgs {
   int na, nr;
   int flags;             // FWD: 1 = mask the input and sum |.|^2, 4 = write out2;
                          // A: 1 = no Xt input, 2 = store X (RM) instead of F_eta X (B4);
-                         // T: 4 = safeguard (support change against supp_old, out2 =
-                         //    F_eta X+ - in1 and its squared norm), 1 = in1 is 0,
+                         // T: 4 = safeguard (support change against supp_old),
                          //    16 = also store X+ (spatial, row-major) to out3
   float scale;           // 1 / N_a (inverse transforms)
   float mu, sigma;       // A: step and threshold lambda*mu
-  float* partials;       // per-block partial sums (R, masked FWD, D, N, safeguarded T)
+  float* partials;       // per-block partial sums (R, masked FWD, D, N)
   float* hist_out;       // R, masked FWD: where the total ||R||^2 goes (may be NULL; the
                          // passes write per-block partials, a one-block kernel the total)
   unsigned* status;      // bit 0: non-finite norm (set by the one-block total kernels)
@@ -1360,17 +1359,6 @@ __device__ __forceinline__ float col_unit(const ColArgs& a, int tile, int b, int
       for (int k = 0; k < E; ++k) o3.st(v[k], ar.voff, k * ar.kstep);
     }
     if (!(a.flags & 2)) fft_line<P, false, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
-    if (a.flags & 4) {
-      // F_eta (X+ - X) and its squared norm (X = 0 with flag 1: an empty
-      // buffer range, every load returns 0)
-      const Buf xo(a.in1, (a.flags & 1) ? 0u : b4b);
-#pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const float2 dk = csub(v[k], xo.f2(ab.voff, k * ab.kstep));
-        acc = fmaf(dk.x, dk.x, fmaf(dk.y, dk.y, acc));
-        out2.st(dk, ab.voff, k * ab.kstep);
-      }
-    }
   } else {  // COL_R: GX = F^-1[W] / N_a; R = m o y - m o GX; out = F R
     fft_line<P, true, C, TwLds, 0, HSC, P::SPLIT>(v, lb, lc, lds, tws, hp);
     // split plans, screened passes: m o y in chunks of 8 after the transform
@@ -1485,14 +1473,11 @@ __global__ __launch_bounds__(P::CT, ColLds<P>::waves_per_eu) void col_pass_kerne
     if (threadIdx.x == 0) a.partials[blockIdx.x] = part;  // reduced by reduce_partials_kernel
   }
   if constexpr (MODE == COL_T) {
-    // safeguard: whether the support moved (any block), ||F_eta (X+ - X)||^2,
-    // and the shrink loop goes on only after a support change
-    // (per-block partials and the change flag; a one-block kernel after this
-    // pass forms the total and the flag, see the residual pass)
+    // safeguard: whether the support moved (any block); the shrink loop goes
+    // on only after a support change (a one-block kernel after this pass
+    // sets the loop's flag)
     if (a.flags & 4) {
       if (__syncthreads_or((int)chg) && threadIdx.x == 0) atomicOr(&a.ad->changed, 1u);
-      const float part = block_sum<CT>(acc, red);
-      if (threadIdx.x == 0) a.partials[blockIdx.x] = part;
     }
   }
   if constexpr (MODE == COL_D) {
