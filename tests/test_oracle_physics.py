@@ -127,3 +127,31 @@ def test_echo_columns_have_unit_norm_before_wrapping():
     assert abs(np.linalg.norm(v) - 1.0) < 1e-12
     # window sizes: Tp*fs range samples, ba/Ka*prf pulses
     assert abs(len(set(c.tolist())) - p["Tp"] * p["fs"]) <= 2
+
+
+def test_add_noise_follows_its_snr_definition():
+    # The measurement model of eq. (model): y = m o (G x + n), the noise scaled
+    # so that the mean signal power over the sampled pixels is snr_db above
+    # the noise power.  With unit-modulus "noise" the added power is exactly
+    # s^2 on every sampled pixel, which pins the scale; unsampled pixels are 0.
+    rng = np.random.default_rng(3)
+    shape = (16, 24)
+    clean = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    mask = rng.random(shape) < 0.4
+    phase = np.exp(2j * np.pi * rng.random(shape))
+    for snr in (0.0, 10.0, 20.0, 35.0):
+        y = sim.add_noise(clean, mask, snr, phase)
+        assert np.all(y[~mask] == 0)
+        added = np.abs(y[mask] - clean[mask]) ** 2
+        p_sig = np.mean(np.abs(clean[mask]) ** 2)
+        np.testing.assert_allclose(added, p_sig / 10 ** (snr / 10), rtol=1e-12)
+        assert 10 * np.log10(p_sig / np.mean(added)) == pytest.approx(snr, abs=1e-9)
+    # Gaussian noise of unit variance: the realised SNR is within sampling error
+    n = inputs.circular_noise((256, 256), 7)
+    big = rng.standard_normal((256, 256)) + 1j * rng.standard_normal((256, 256))
+    m = np.ones((256, 256), dtype=bool)
+    y = sim.add_noise(big, m, 20.0, n)
+    snr = 10 * np.log10(np.mean(np.abs(big) ** 2) / np.mean(np.abs(y - big) ** 2))
+    assert snr == pytest.approx(20.0, abs=0.05)
+    # no sampled pixel: nothing to scale against, all zeros
+    assert np.all(sim.add_noise(clean, np.zeros(shape, dtype=bool), 20.0, phase) == 0)
