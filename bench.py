@@ -59,7 +59,8 @@ KIND_SYMBOL = {
 # library's column_variant and row_variant)
 KIND_VARIANT = {("col_residual", 4096): 1, ("col_update_threshold", 4096): 2,
                 ("col_update_sparse", 4096): 2, ("col_update_threshold", 2048): 1,
-                ("col_update_sparse", 2048): 1, ("row_M", 8192): 1, ("row_G", 8192): 1,
+                ("col_update_sparse", 2048): 1, ("col_residual", 2048): 1, ("row_M", 8192): 1,
+                ("row_G", 8192): 1,
                 ("col_fwd", 8192): 1, ("col_inv", 8192): 1}
 
 

@@ -167,7 +167,7 @@ int column_variant(int n, int which) {
   if (n == 8192) return (which == CK_FWD || which == CK_INV) ? 1 : 0;
   if (n == 4096 && which == CK_R) return 1;
   if (n == 4096 && (which == CK_A || which == CK_AS || which == CK_VB)) return 2;
-  if (n == 2048 && (which == CK_A || which == CK_AS || which == CK_VB)) return 1;
+  if (n == 2048 && (which == CK_A || which == CK_AS || which == CK_VB || which == CK_R)) return 1;
   return 0;
 }
 
